@@ -1,0 +1,135 @@
+#!/usr/bin/env python
+"""Seconds per geometry for SCCSD(E) energies + gradients + couplings on one
+MI355X, with the FP64 MFMA contraction roofline and the CPU oracle timed on a
+bounded sample.  Prints one JSON line.
+
+Workload (default o10v90): synthetic Cholesky-factored Hamiltonian with
+o = 10, v = 90, N_J = 300, 3 excited states, 36 coordinates, 3 pairwise
+couplings; per step: set Hamiltonian (cold start), SCCSD(E) ground + excited
+states, gradients of all 3 states, 3 couplings over all coordinates.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="o10v90")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2403_01007_amd import Context
+    from synth_inputs import make_system
+
+    S = make_system(args.workload)
+    h, L = S.at(np.zeros(S.ncoord))
+    dev = torch.device("cuda:0")
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11, verbose=args.verbose)
+    h_d = torch.as_tensor(h, device=dev)
+    L_d = torch.as_tensor(L, device=dev)
+    dh = torch.as_tensor(S.dh, device=dev)
+    dL = torch.as_tensor(S.dL, device=dev)
+    flops = [0.0]
+
+    def step():
+        ctx.set_hamiltonian(h_d, L_d)
+        E, zeta, info = ctx.excited()
+        flops[0] += info.flops_mfma
+        out = {"E": E, "zeta": zeta}
+        for n in range(S.nstates):
+            g, info = ctx.gradient(n, dh, dL)
+            flops[0] += info.flops_mfma
+            out[f"g{n}"] = g
+        for (m, n) in S.nacs:
+            d, info = ctx.nac(m, n, dh, dL)
+            flops[0] += info.flops_mfma
+            out[f"d{m}{n}"] = d
+        return out
+
+    for _ in range(args.warmup):
+        step()
+        print(f"[warmup step done]", file=sys.stderr, flush=True)
+    flops[0] = 0.0
+    ms0, fl0, n0 = ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = step()
+        print(f"[timed step {k} done]", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms1, fl1, n1 = ctx.profile(False)
+    s_per_geom = elapsed / args.steps
+    gemm_s = (ms1 - ms0) / 1e3
+    gemm_fl = fl1 - fl0
+    achieved = gemm_fl / gemm_s / 1e12 if gemm_s > 0 else 0.0
+
+    # flops of one residual evaluation (for the CPU-baseline scaling)
+    nov = S.o * S.v
+    t_zero = np.zeros(nov + nov * nov)
+    ctx.profile(True)
+    a_ms, a_fl, _ = ctx.profile(True)
+    ctx.eval_residual(t_zero)
+    b_ms, b_fl, _ = ctx.profile(False)
+    res_flops = b_fl - a_fl
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import cc
+        threads = len(os.sched_getaffinity(0))
+        torch.set_num_threads(threads)
+        ht = torch.as_tensor(h)
+        gt = torch.einsum("Jpq,Jrs->pqrs", torch.as_tensor(L), torch.as_tensor(L))
+        t1 = torch.zeros((S.v, S.o), dtype=torch.float64)
+        t2 = torch.zeros((S.v, S.o, S.v, S.o), dtype=torch.float64)
+        cc.residual(ht, gt, t1, t2, S.o)
+        nrep, tc = 0, 0.0
+        while tc < 10.0 and nrep < 20:
+            c0 = time.perf_counter()
+            cc.residual(ht, gt, t1, t2, S.o)
+            tc += time.perf_counter() - c0
+            nrep += 1
+        per_res = tc / nrep
+        equiv = (flops[0] / args.steps) / res_flops if res_flops > 0 else float("nan")
+        cpu = {"value": per_res * equiv, "unit": "s/geometry", "cores": threads, "kind": "oracle",
+               "sample": (f"{nrep} oracle CCSD residual evaluations at {args.workload} "
+                          f"({per_res:.2f} s each, full N^4 integrals, torch CPU FP64), scaled by the "
+                          f"{equiv:.0f} residual-equivalents of contraction flops one GPU geometry executes")}
+
+    line = {
+        "metric": "s/geometry (energies+gradients+NACs), MFMA TFLOP/s; mixed+learned vs FP64",
+        "value": s_per_geom, "unit": "s/geometry", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * s_per_geom, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "o": S.o, "v": S.v, "nchol": S.nj, "nstates": S.nstates,
+                   "ncoord": S.ncoord, "nacs": len(S.nacs), "precision": "fp64", "guess": "mp2/unit",
+                   "generator": S.reading},
+        "tflops_contractions": (flops[0] / args.steps) / s_per_geom / 1e12,
+        "roofline": {"bound": "mfma", "kernel": "gemm_f64_kernel", "achieved": achieved,
+                     "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA,
+                     "traffic": None, "launches": n1 - n0, "kernel_seconds": gemm_s},
+        "cpu_baseline": cpu,
+        "energies": [float(x) for x in res["E"]],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * scc.h -- C ABI of libscc: SCCSD(E) energies, nuclear gradients and
+ * nonadiabatic derivative couplings on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: similarity constrained coupled cluster singles and doubles with the
+ * natural projection, gradients and couplings from the Lagrangian (Z-vector)
+ * method of Kjonstad, Angelico and Koch, "Coupled cluster theory for
+ * nonadiabatic dynamics: nuclear gradients and nonadiabatic couplings in
+ * similarity constrained coupled cluster theory" (arXiv:2403.01007).
+ *
+ * Conventions shared by every call
+ *   - Closed-shell restricted reference, o occupied and v virtual spatial
+ *     orbitals, N = o + v; occupied orbitals first.
+ *   - H = sum h_pq E_pq + 1/2 sum g_pqrs (E_pq E_rs - d_qr E_ps),
+ *     g_pqrs = sum_J L^J_pq L^J_rs (Cholesky-factored two-electron integrals).
+ *   - Amplitude layouts (row-major FP64): t1[a][i] (v x o) and
+ *     t2[a][i][b][j] (v x o x v x o), symmetric under (ai) <-> (bj), with
+ *     T2 = 1/2 sum_aibj t_aibj E_ai E_bj.  An excited-state vector is
+ *     [R0 | R1 (v*o) | R2 (v*o*v*o)].  Left vectors pair with right vectors
+ *     through the plain dot product over this full layout.
+ *   - Units: Hartree; coordinates are dimensionless.
+ *
+ * Memory and streams
+ *   - Every array argument is a DEVICE pointer (HIP global memory) unless a
+ *     comment says "host".  The caller owns all buffers, including the
+ *     workspace; the library never allocates device memory and never keeps a
+ *     caller pointer after a call returns (the Hamiltonian is copied into the
+ *     workspace).
+ *   - All work is enqueued on the stream given to scc_create; calls are
+ *     blocking (they synchronise that stream before returning) because the
+ *     solvers read residual norms back to the host.
+ *
+ * Errors: every int-returning call returns one of the SCC_* codes below and
+ * never throws.  On error, outputs other than scc_info are unspecified and
+ * scc_last_error() describes the failure.
+ */
+#ifndef SCC_H
+#define SCC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SCC_OK = 0,
+  SCC_EINVAL = -1,     /* bad dimensions, NULL pointer or option */
+  SCC_ESTATE = -2,     /* call made out of order */
+  SCC_ENOCONV = -3,    /* iteration limit reached */
+  SCC_ECOMPLEX = -4,   /* a converged excited-state energy is complex */
+  SCC_ESINGULAR = -5,  /* singular linear system (e.g. omega_m ~ 0) */
+  SCC_EDEVICE = -6,    /* HIP runtime error */
+  SCC_ENOMEM = -7      /* workspace smaller than scc_workspace_bytes */
+};
+
+typedef struct scc_dims {
+  int nocc;     /* o */
+  int nvirt;    /* v */
+  int nchol;    /* Cholesky rank N_J */
+  int nstates;  /* excited states in the constrained set K (>= 1) */
+} scc_dims;
+
+typedef struct scc_options {
+  double tol_residual;   /* max-norm of CC / EOM / multiplier residuals (e.g. 1e-10) */
+  double tol_overlap;    /* |O_kl| threshold of the SCC constraint (e.g. 1e-11) */
+  int max_iter;          /* iteration limit of each solver */
+  int scc;               /* 1: SCCSD(E); 0: plain CCSD / EOM-CCSD */
+  int verbose;           /* 1: per-iteration log on stderr */
+} scc_options;
+
+typedef struct scc_info {
+  int iterations;        /* solver iterations of the call */
+  int converged;         /* 1 on success */
+  int fallback_used;     /* 1 if a supplied guess was rejected */
+  double residual;       /* final residual norm */
+  double seconds;        /* wall time of the call */
+  double flops_mfma;     /* FP64 contraction flops executed by the call */
+} scc_info;
+
+typedef struct scc_ctx scc_ctx;
+
+/* Workspace size (bytes) for the given dimensions.  Host pointers; pure
+ * host computation.  Returns SCC_EINVAL for bad dimensions. */
+int scc_workspace_bytes(const scc_dims* dims, const scc_options* opts, size_t* bytes);
+
+/* Create a context.  workspace: device buffer of >= scc_workspace_bytes
+ * bytes (256-byte aligned); hip_stream: hipStream_t (NULL = default stream).
+ * Returns SCC_ENOMEM if the workspace is too small. */
+int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, size_t bytes,
+               void* hip_stream, scc_ctx** ctx);
+void scc_destroy(scc_ctx* ctx);
+/* Message of the last failure of this context (host string, owned by ctx). */
+const char* scc_last_error(const scc_ctx* ctx);
+
+/* Hamiltonian of the current geometry in its canonical restricted
+ * Hartree-Fock molecular-orbital basis (orbital energies ascending within
+ * the occupied and the virtual blocks):
+ *   h    [N][N]         one-electron integrals,
+ *   chol [N_J][N][N]    Cholesky vectors, symmetric in the last two indices.
+ * Copies into the workspace; invalidates every cached solution and resets
+ * the amplitudes (t = 0, so the first ground-state step is MP2). Returns
+ * SCC_EINVAL if max |F_ai| > 1e-6 (not a Hartree-Fock basis). */
+int scc_set_hamiltonian(scc_ctx* ctx, const double* h, const double* chol, double e_nuc);
+
+/* Ground state Omega(t) = 0 of CCSD (zeta = 0) (coupled cluster section,
+ * eq. for Omega_mu).  guess_t: NULL or [t1 | t2]; e0: device double[1]. */
+int scc_ground(scc_ctx* ctx, const double* guess_t, double* e0, scc_info* info);
+
+/* Excited states of the constrained set: EOM right/left eigenvectors with the
+ * SCC orthogonality conditions O_kl = <psi_k|P|psi_l> = 0 imposed through
+ * zeta_kl X3^kl, ground and excited states solved simultaneously (SCC
+ * section; natural projection).  Normalisation: O_kk = 1 and calL_k.calR_k =
+ * 1; phase: largest |R1| element positive; order: ascending energy.
+ * energies: device double[nstates] (total energies);
+ * zeta: device double[nstates*(nstates-1)/2] (pairs k<l, row-major). */
+int scc_excited(scc_ctx* ctx, int nstates, const double* guess, double* energies, double* zeta, scc_info* info);
+
+/* Lagrange multipliers of the gradient of state n (kind = 0, m ignored) or
+ * of the coupling d_mn (kind = 1): the stationarity conditions of the
+ * gradient / coupling Lagrangians (eqs. Lagrangian_gradient,
+ * Lagrangian_coupling) solved for the amplitude, excited-state and
+ * orthogonality multipliers first, then the orbital multipliers. */
+int scc_multipliers(scc_ctx* ctx, int kind, int m, int n, scc_info* info);
+
+/* Effective densities of the last multiplier solve: d1 [N][N] = dL/dh,
+ * z3 [N_J][N][N] = dL/dL^J (MO basis), kappa_bar [v][o].  Any may be NULL. */
+int scc_densities(scc_ctx* ctx, double* d1, double* z3, double* kappa_bar);
+
+/* Gradient g_n (eq. gradient_expression) along ncoord coordinates whose
+ * derivative integrals, in the same MO basis, are dh [ncoord][N][N] and
+ * dchol [ncoord][N_J][N][N]: g[k] = <dh_k, d1> + <dchol_k, z3>.
+ * grad: device double[ncoord]. */
+int scc_gradient(scc_ctx* ctx, int n, int ncoord, const double* dh, const double* dchol, double* grad,
+                 scc_info* info);
+
+/* Derivative coupling d_mn = <psi_m| d psi_n / dx> (derivative on the ket;
+ * eq. coupling_expression with a fixed orthonormal basis, so O^(1)_mn = 0). */
+int scc_nac(scc_ctx* ctx, int m, int n, int ncoord, const double* dh, const double* dchol, double* nac,
+            scc_info* info);
+
+/* Export solution fields to device buffers:
+ *   SCC_FIELD_T      [t1 | t2]
+ *   SCC_FIELD_R      right vector k  [R0 | R1 | R2]
+ *   SCC_FIELD_L      left vector k   [L0 | L1 | L2]
+ *   SCC_FIELD_E0     ground-state energy (1)
+ *   SCC_FIELD_OMEGA  residual [Omega1 | Omega2] at the current amplitudes */
+enum { SCC_FIELD_T = 0, SCC_FIELD_R = 1, SCC_FIELD_L = 2, SCC_FIELD_E0 = 3, SCC_FIELD_OMEGA = 4 };
+int scc_get(scc_ctx* ctx, int field, int k, double* out);
+
+/* Profiling of the FP64 MFMA contraction kernel: enable = 1 starts timing
+ * every GEMM launch with HIP events on the context's stream (0 stops and
+ * clears nothing).  On return (host pointers, any may be NULL): accumulated
+ * kernel milliseconds, algorithmic flops (2 M N K per launch) and launches
+ * since the context was created. */
+int scc_profile(scc_ctx* ctx, int enable, double* gemm_ms, double* gemm_flops, long long* gemm_launches);
+
+/* Test hooks on the device programs (inputs/outputs device pointers):
+ *   residual at given amplitudes (and zeta / X3 states when nstates > 1):
+ *     t [t1|t2], zeta [npairs], xs [nstates][1+nov+nov^2] (may be NULL);
+ *     out [E0 | Omega1 | Omega2]
+ *   right transformation of vec [R0|R1|R2] at the current amplitudes
+ *     -> out [sigma0 | sigma1 | sigma2]
+ *   left transformation of vec -> out (same layout; doubles part symmetrised,
+ *   i.e. the transformation restricted to (ai)<->(bj) symmetric vectors). */
+int scc_eval_residual(scc_ctx* ctx, const double* t, const double* zeta, const double* xs, double* out);
+int scc_eval_sigma(scc_ctx* ctx, const double* vec, double* out);
+int scc_eval_left(scc_ctx* ctx, const double* vec, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCC_H */

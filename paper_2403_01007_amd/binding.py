@@ -1,0 +1,230 @@
+"""ctypes binding of libscc (same names as the C ABI in include/scc.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+SCC_OK = 0
+ERRORS = {0: "SCC_OK", -1: "SCC_EINVAL", -2: "SCC_ESTATE", -3: "SCC_ENOCONV", -4: "SCC_ECOMPLEX",
+          -5: "SCC_ESINGULAR", -6: "SCC_EDEVICE", -7: "SCC_ENOMEM"}
+FIELD_T, FIELD_R, FIELD_L, FIELD_E0, FIELD_OMEGA = 0, 1, 2, 3, 4
+
+EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_last_error",
+                    "scc_set_hamiltonian", "scc_ground", "scc_excited", "scc_multipliers",
+                    "scc_densities", "scc_gradient", "scc_nac", "scc_get", "scc_eval_residual",
+                    "scc_eval_sigma", "scc_eval_left", "scc_profile"]
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("nocc", ctypes.c_int), ("nvirt", ctypes.c_int), ("nchol", ctypes.c_int),
+                ("nstates", ctypes.c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tol_residual", ctypes.c_double), ("tol_overlap", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("scc", ctypes.c_int), ("verbose", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("fallback_used", ctypes.c_int),
+                ("residual", ctypes.c_double), ("seconds", ctypes.c_double), ("flops_mfma", ctypes.c_double)]
+
+
+class SccError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def library_path():
+    return os.path.join(HERE, "libscc.so")
+
+
+def load_library():
+    """Load the in-tree libscc.so; raise if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"libscc.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lib.scc_workspace_bytes.argtypes = [ctypes.POINTER(Dims), ctypes.POINTER(Options), ctypes.POINTER(S)]
+    lib.scc_create.argtypes = [ctypes.POINTER(Dims), ctypes.POINTER(Options), P, S, P, ctypes.POINTER(P)]
+    lib.scc_destroy.argtypes = [P]
+    lib.scc_destroy.restype = None
+    lib.scc_last_error.argtypes = [P]
+    lib.scc_last_error.restype = ctypes.c_char_p
+    lib.scc_set_hamiltonian.argtypes = [P, P, P, D]
+    lib.scc_ground.argtypes = [P, P, P, ctypes.POINTER(Info)]
+    lib.scc_excited.argtypes = [P, I, P, P, P, ctypes.POINTER(Info)]
+    lib.scc_multipliers.argtypes = [P, I, I, I, ctypes.POINTER(Info)]
+    lib.scc_densities.argtypes = [P, P, P, P]
+    lib.scc_gradient.argtypes = [P, I, I, P, P, P, ctypes.POINTER(Info)]
+    lib.scc_nac.argtypes = [P, I, I, I, P, P, P, ctypes.POINTER(Info)]
+    lib.scc_get.argtypes = [P, I, I, P]
+    lib.scc_eval_residual.argtypes = [P, P, P, P, P]
+    lib.scc_eval_sigma.argtypes = [P, P, P]
+    lib.scc_eval_left.argtypes = [P, P, P]
+    lib.scc_profile.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]
+    for name in EXPORTED_SYMBOLS:
+        fn = getattr(lib, name)
+        if name not in ("scc_destroy", "scc_last_error"):
+            fn.restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def workspace_bytes(o, v, nj, nstates, opts=None):
+    lib = load_library()
+    d = Dims(o, v, nj, nstates)
+    n = ctypes.c_size_t(0)
+    rc = lib.scc_workspace_bytes(ctypes.byref(d), ctypes.byref(opts) if opts else None, ctypes.byref(n))
+    if rc != SCC_OK:
+        raise SccError(rc, "workspace size")
+    return n.value
+
+
+class Context:
+    """Owns a libscc context plus its workspace (a torch uint8 CUDA tensor)."""
+
+    def __init__(self, o, v, nj, nstates, tol=1e-10, tol_overlap=1e-11, max_iter=200, scc=True,
+                 verbose=False, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.o, self.v, self.nj, self.ns = o, v, nj, nstates
+        self.n = o + v
+        self.nov = o * v
+        self.device = torch.device(device)
+        self.opts = Options(tol, tol_overlap, max_iter, 1 if scc else 0, 1 if verbose else 0)
+        self.dims = Dims(o, v, nj, nstates)
+        nbytes = ctypes.c_size_t(0)
+        self._check(self.lib.scc_workspace_bytes(ctypes.byref(self.dims), ctypes.byref(self.opts),
+                                                 ctypes.byref(nbytes)), None)
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.scc_create(ctypes.byref(self.dims), ctypes.byref(self.opts),
+                                 ctypes.c_void_p(self.workspace.data_ptr()), nbytes.value + 256,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != SCC_OK:
+            raise SccError(rc, "scc_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.scc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != SCC_OK:
+            msg = self.lib.scc_last_error(self.h).decode() if getattr(self, "h", None) else ""
+            raise SccError(rc, f"{what}: {msg}")
+
+    def _dev(self, a):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(device=self.device, dtype=t.float64).contiguous()
+        return t.as_tensor(a, dtype=t.float64).to(self.device).contiguous()
+
+    def zeros(self, *shape):
+        return self.torch.zeros(*shape, dtype=self.torch.float64, device=self.device)
+
+    # --- calls ---------------------------------------------------------------
+    def set_hamiltonian(self, h, chol, e_nuc=0.0):
+        self._h = self._dev(h)
+        self._L = self._dev(chol)
+        self._check(self.lib.scc_set_hamiltonian(self.h, _ptr(self._h), _ptr(self._L), float(e_nuc)),
+                    "scc_set_hamiltonian")
+
+    def ground(self, guess=None):
+        e0 = self.zeros(1)
+        info = Info()
+        g = None if guess is None else self._dev(guess)
+        self._check(self.lib.scc_ground(self.h, _ptr(g), _ptr(e0), ctypes.byref(info)), "scc_ground")
+        return float(e0.cpu()[0]), info
+
+    def excited(self):
+        e = self.zeros(self.ns)
+        z = self.zeros(max(1, self.ns * (self.ns - 1) // 2))
+        info = Info()
+        self._check(self.lib.scc_excited(self.h, self.ns, None, _ptr(e), _ptr(z), ctypes.byref(info)),
+                    "scc_excited")
+        return e.cpu().numpy(), z.cpu().numpy()[:self.ns * (self.ns - 1) // 2], info
+
+    def multipliers(self, kind, m, n):
+        info = Info()
+        self._check(self.lib.scc_multipliers(self.h, kind, m, n, ctypes.byref(info)), "scc_multipliers")
+        return info
+
+    def densities(self):
+        d1 = self.zeros(self.n, self.n)
+        z3 = self.zeros(self.nj, self.n, self.n)
+        kb = self.zeros(self.v, self.o)
+        self._check(self.lib.scc_densities(self.h, _ptr(d1), _ptr(z3), _ptr(kb)), "scc_densities")
+        return d1, z3, kb
+
+    def gradient(self, n, dh, dchol):
+        dh, dl = self._dev(dh), self._dev(dchol)
+        out = self.zeros(dh.shape[0])
+        info = Info()
+        self._check(self.lib.scc_gradient(self.h, n, dh.shape[0], _ptr(dh), _ptr(dl), _ptr(out),
+                                          ctypes.byref(info)), "scc_gradient")
+        return out.cpu().numpy(), info
+
+    def nac(self, m, n, dh, dchol):
+        dh, dl = self._dev(dh), self._dev(dchol)
+        out = self.zeros(dh.shape[0])
+        info = Info()
+        self._check(self.lib.scc_nac(self.h, m, n, dh.shape[0], _ptr(dh), _ptr(dl), _ptr(out),
+                                     ctypes.byref(info)), "scc_nac")
+        return out.cpu().numpy(), info
+
+    def get(self, field, k=0):
+        nvt = self.nov + self.nov * self.nov
+        size = {FIELD_T: nvt, FIELD_R: 1 + nvt, FIELD_L: 1 + nvt, FIELD_E0: 1, FIELD_OMEGA: nvt}[field]
+        out = self.zeros(size)
+        self._check(self.lib.scc_get(self.h, field, k, _ptr(out)), "scc_get")
+        return out
+
+    def eval_residual(self, t, zeta=None, xs=None):
+        out = self.zeros(1 + self.nov + self.nov * self.nov)
+        t = self._dev(t)
+        z = None if zeta is None else self._dev(zeta)
+        x = None if xs is None else self._dev(xs)
+        self._check(self.lib.scc_eval_residual(self.h, _ptr(t), _ptr(z), _ptr(x), _ptr(out)),
+                    "scc_eval_residual")
+        return out
+
+    def eval_sigma(self, vec):
+        out = self.zeros(1 + self.nov + self.nov * self.nov)
+        v = self._dev(vec)
+        self._check(self.lib.scc_eval_sigma(self.h, _ptr(v), _ptr(out)), "scc_eval_sigma")
+        return out
+
+    def profile(self, enable):
+        ms, fl, n = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_longlong(0)
+        self._check(self.lib.scc_profile(self.h, 1 if enable else 0, ctypes.byref(ms), ctypes.byref(fl),
+                                         ctypes.byref(n)), "scc_profile")
+        return ms.value, fl.value, n.value
+
+    def eval_left(self, vec):
+        out = self.zeros(1 + self.nov + self.nov * self.nov)
+        v = self._dev(vec)
+        self._check(self.lib.scc_eval_left(self.h, _ptr(v), _ptr(out)), "scc_eval_left")
+        return out

@@ -1,0 +1,737 @@
+// HIP kernels for gfx950 and the executor of contraction programs.
+//
+// * gemm_f64: FP64 matrix-core (v_mfma_f64_16x16x4_f64) GEMM over strided
+//   operands.  A 64x64 output tile per 256-thread workgroup (4 wave64s, each
+//   32x32 = 2x2 MFMA tiles), K staged through LDS in slabs of 16.  Global
+//   loads are mapped so that consecutive lanes walk the operand's unit-stride
+//   dimension.
+// * perm: strided N-d gather/scatter with up to four weighted inputs; used
+//   for operand packing, output permutation, linear combinations, block
+//   slices and embeddings.
+// * dot: two-pass deterministic reduction (no floating-point atomics).
+#include <algorithm>
+#include <cstdio>
+#include <stdexcept>
+
+#include "exec.hpp"
+
+namespace scc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, GEMM_THREADS = 256;
+
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs a) {
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int64_t split = a.splits > 1 ? blockIdx.z : 0;
+  const int64_t bz = a.splits > 1 ? 0 : blockIdx.z;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const double* A = a.A + bz * a.sAb;
+  const double* B = a.B + bz * a.sBb;
+  const int64_t kbeg = a.splits > 1 ? split * a.kchunk : 0;
+  const int64_t kend = a.splits > 1 ? min(a.K, kbeg + a.kchunk) : a.K;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 32;
+  const int wn = (wave & 1) * 32;
+  const bool a_kfast = (a.sAk == 1);
+  const bool b_nfast = (a.sBn == 1) || (a.sBk != 1);
+  d4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int e = 0; e < (BM * BK) / GEMM_THREADS; ++e) {
+      const int idx = tid + e * GEMM_THREADS;
+      int mm, kk;
+      if (a_kfast) {
+        kk = idx % BK;
+        mm = idx / BK;
+      } else {
+        mm = idx % BM;
+        kk = idx / BM;
+      }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      As[kk][mm] = (gm < a.M && gk < kend) ? A[gm * a.sAm + gk * a.sAk] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < (BN * BK) / GEMM_THREADS; ++e) {
+      const int idx = tid + e * GEMM_THREADS;
+      int nn, kk;
+      if (b_nfast) {
+        nn = idx % BN;
+        kk = idx / BN;
+      } else {
+        kk = idx % BK;
+        nn = idx / BK;
+      }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      Bs[kk][nn] = (gn < a.N && gk < kend) ? B[gk * a.sBk + gn * a.sBn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        af[t] = As[kr][wm + t * 16 + (lane & 15)];
+        bf[t] = Bs[kr][wn + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (a.splits > 1) {
+    double* P = a.P + split * a.M * a.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wm + i * 16 + r * 4 + (lane >> 4);
+          const int64_t col = n0 + wn + j * 16 + (lane & 15);
+          if (row < a.M && col < a.N) P[row * a.N + col] = a.alpha * acc[i][j][r];
+        }
+    return;
+  }
+  const double* Cin = a.Cin ? a.Cin + bz * a.sCb : nullptr;
+  double* C = a.C + bz * a.sCb;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // v_mfma_f64_16x16x4_f64: lane l, register r holds D[4 r + l / 16][l % 16]
+        const int64_t row = m0 + wm + i * 16 + r * 4 + (lane >> 4);
+        const int64_t col = n0 + wn + j * 16 + (lane & 15);
+        if (row < a.M && col < a.N) {
+          double v = a.alpha * acc[i][j][r];
+          if (Cin) v += a.beta * Cin[row * a.sCm + col * a.sCn];
+          C[row * a.sCm + col * a.sCn] = v;
+        }
+      }
+}
+
+__global__ void splitk_reduce_kernel(GemmArgs a) {
+  const int64_t mn = a.M * a.N;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mn; i += stride) {
+    const int64_t row = i / a.N, col = i % a.N;
+    double v = 0.0;
+    for (int64_t s = 0; s < a.splits; ++s) v += a.P[s * mn + i];
+    if (a.Cin) v += a.beta * a.Cin[row * a.sCm + col * a.sCn];
+    a.C[row * a.sCm + col * a.sCn] = v;
+  }
+}
+
+__global__ void perm_kernel(PermArgs a) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < a.total; lin += stride) {
+    int64_t rem = lin, oo = 0;
+    int64_t io[4] = {0, 0, 0, 0};
+    for (int d = a.nd - 1; d >= 0; --d) {
+      const int64_t x = rem % a.dim[d];
+      rem /= a.dim[d];
+      oo += x * a.ostr[d];
+      for (int i = 0; i < a.nin; ++i) io[i] += x * a.istr[i][d];
+    }
+    double v = 0.0;
+    for (int i = 0; i < a.nin; ++i) v += a.coef[i] * a.in[i][io[i]];
+    if (a.addend) v += a.beta * a.addend[oo];
+    a.out[oo] = v;
+  }
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+constexpr int RED_THREADS = 256, RED_BLOCKS = 1024;
+
+__device__ double block_sum(double v) {
+  __shared__ double sh[RED_THREADS];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(RED_THREADS) void dot_partial_kernel(const double* x, const double* y, int64_t n,
+                                                                  double* partials) {
+  double v = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) v += x[i] * y[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void dot_final_kernel(const double* partials, int nblocks, double alpha,
+                                                                const double* addend, double beta, double* out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) v += partials[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) out[0] = alpha * v + (addend ? beta * addend[0] : 0.0);
+}
+
+__global__ void axpby_kernel(double a, const double* x, double b, double* y, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void precond_kernel(const double* x, const double* d, double shift, double fl, double* y, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double den = d[i] - shift;
+    if (fabs(den) < fl) den = den < 0 ? -fl : fl;
+    y[i] = x[i] / den;
+  }
+}
+
+__global__ void sym_pairs_kernel(double* x, int64_t nov) {
+  const int64_t total = nov * nov;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t p = i / nov, q = i % nov;
+    if (p < q) {
+      const double v = 0.5 * (x[p * nov + q] + x[q * nov + p]);
+      x[p * nov + q] = v;
+      x[q * nov + p] = v;
+    }
+  }
+}
+
+// one block per coordinate: grad[k] = <dh_k, D1> + <dL_k, Z>
+__global__ __launch_bounds__(RED_THREADS) void deriv_contract_kernel(const double* dh, int64_t nh, const double* D1,
+                                                                     const double* dL, int64_t nl, const double* Z,
+                                                                     double* partials, int chunks) {
+  const int k = blockIdx.y;
+  const int c = blockIdx.x;
+  const double* h = dh + (int64_t)k * nh;
+  const double* l = dL + (int64_t)k * nl;
+  double v = 0.0;
+  const int64_t stride = (int64_t)chunks * blockDim.x;
+  for (int64_t i = (int64_t)c * blockDim.x + threadIdx.x; i < nh; i += stride) v += h[i] * D1[i];
+  for (int64_t i = (int64_t)c * blockDim.x + threadIdx.x; i < nl; i += stride) v += l[i] * Z[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) partials[(int64_t)k * chunks + c] = v;
+}
+
+__global__ void deriv_final_kernel(const double* partials, int chunks, int ncoord, double* grad) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ncoord) {
+    double v = 0.0;
+    for (int c = 0; c < chunks; ++c) v += partials[(int64_t)k * chunks + c];
+    grad[k] = v;
+  }
+}
+
+static void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static unsigned grid_for(int64_t n, int threads = 256) {
+  int64_t b = (n + threads - 1) / threads;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+}
+
+void launch_gemm(const GemmArgs& a, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return;
+  if (a.splits > 1 && (a.batch != 1 || !a.P || a.kchunk <= 0)) throw std::runtime_error("bad split-K plan");
+  dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((a.M + BM - 1) / BM),
+            (unsigned)(a.splits > 1 ? a.splits : a.batch));
+  if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm grid too large");
+  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(GEMM_THREADS), 0, s, a);
+  check(hipGetLastError(), "gemm launch");
+  if (a.splits > 1) {
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(a.M * a.N)), dim3(256), 0, s, a);
+    check(hipGetLastError(), "split-K reduce launch");
+  }
+}
+
+void launch_perm(const PermArgs& a, hipStream_t s) {
+  if (a.total <= 0) return;
+  hipLaunchKernelGGL(perm_kernel, dim3(grid_for(a.total)), dim3(256), 0, s, a);
+  check(hipGetLastError(), "perm launch");
+}
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  check(hipGetLastError(), "fill launch");
+}
+
+void launch_dot(const double* x, const double* y, int64_t n, double alpha, const double* addend, double beta,
+                double* out, double* partials, hipStream_t s) {
+  int nb = (int)std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, (n + RED_THREADS * 4 - 1) / (RED_THREADS * 4)));
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(nb), dim3(RED_THREADS), 0, s, x, y, n, partials);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(RED_THREADS), 0, s, partials, nb, alpha, addend, beta, out);
+  check(hipGetLastError(), "dot launch");
+}
+
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, x, b, y, n);
+  check(hipGetLastError(), "axpby launch");
+}
+
+void launch_precond(const double* x, const double* d, double shift, double fl, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(precond_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, d, shift, fl, y, n);
+  check(hipGetLastError(), "precond launch");
+}
+
+void launch_sym_pairs(double* x, int64_t nov, hipStream_t s) {
+  hipLaunchKernelGGL(sym_pairs_kernel, dim3(grid_for(nov * nov)), dim3(256), 0, s, x, nov);
+  check(hipGetLastError(), "sym launch");
+}
+
+void launch_deriv_contract(const double* dh, int64_t nh, const double* D1, const double* dL, int64_t nl,
+                           const double* Z, int ncoord, double* grad, double* partials, hipStream_t s) {
+  if (ncoord <= 0) return;
+  int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (nl + 256 * 64 - 1) / (256 * 64)));
+  // partials must hold ncoord * chunks doubles
+  hipLaunchKernelGGL(deriv_contract_kernel, dim3(chunks, ncoord), dim3(RED_THREADS), 0, s, dh, nh, D1, dL, nl, Z,
+                     partials, chunks);
+  hipLaunchKernelGGL(deriv_final_kernel, dim3((ncoord + 63) / 64), dim3(64), 0, s, partials, chunks, ncoord, grad);
+  check(hipGetLastError(), "deriv launch");
+}
+
+// ---------------------------------------------------------------------------
+// planning
+// ---------------------------------------------------------------------------
+static std::vector<int64_t> row_major_strides(const TensorDesc& d) {
+  std::vector<int64_t> s(d.nd, 1);
+  for (int i = d.nd - 2; i >= 0; --i) s[i] = s[i + 1] * d.dim[i + 1];
+  return s;
+}
+
+struct View {
+  bool ok;
+  int64_t size, stride;
+};
+
+// Can indices `order` (a subsequence of labels `l`) of a row-major tensor be
+// fused into one dimension (in that order)?
+static View fuse(const std::string& l, const TensorDesc& d, const std::string& order) {
+  auto st = row_major_strides(d);
+  if (order.empty()) return {true, 1, 0};
+  int64_t size = 1;
+  for (size_t i = 0; i < order.size(); ++i) size *= d.dim[l.find(order[i])];
+  for (size_t i = 0; i + 1 < order.size(); ++i) {
+    int p = (int)l.find(order[i]), q = (int)l.find(order[i + 1]);
+    if (st[p] != st[q] * d.dim[q]) return {false, size, 0};
+  }
+  return {true, size, st[l.find(order.back())]};
+}
+
+static std::string filter(const std::string& src, const std::string& keep) {
+  std::string r;
+  for (char c : src)
+    if (keep.find(c) != std::string::npos) r += c;
+  return r;
+}
+
+// gather-copy tensor (labels l) into a contiguous buffer with index order `order`
+static PermArgs pack_args(const TensorDesc& d, const std::string& l, const std::string& order, const double* src,
+                          double* dst) {
+  PermArgs p{};
+  auto st = row_major_strides(d);
+  p.nd = (int)order.size();
+  p.nin = 1;
+  p.in[0] = src;
+  p.coef[0] = 1.0;
+  p.out = dst;
+  p.addend = nullptr;
+  p.beta = 0.0;
+  int64_t total = 1;
+  for (int i = 0; i < p.nd; ++i) {
+    int pos = (int)l.find(order[i]);
+    p.dim[i] = d.dim[pos];
+    p.istr[0][i] = st[pos];
+    total *= p.dim[i];
+  }
+  int64_t s = 1;
+  for (int i = p.nd - 1; i >= 0; --i) {
+    p.ostr[i] = s;
+    s *= p.dim[i];
+  }
+  p.total = total;
+  if (p.nd == 0) {
+    p.nd = 1;
+    p.dim[0] = 1;
+    p.istr[0][0] = 0;
+    p.ostr[0] = 0;
+    p.total = 1;
+  }
+  return p;
+}
+
+ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* scratch) {
+  ContractPlan P;
+  const TensorDesc& dA = g.t[op.a];
+  const TensorDesc& dB = g.t[op.b];
+  const TensorDesc& dO = g.t[op.out];
+  const std::string &la = op.la, &lb = op.lb, &lo = op.lo;
+  std::string bat, mi, ni, ki;
+  for (char c : lo) {
+    bool ia = la.find(c) != std::string::npos, ib = lb.find(c) != std::string::npos;
+    if (ia && ib)
+      bat += c;
+    else if (ia)
+      mi += c;
+    else
+      ni += c;
+  }
+  for (char c : la)
+    if (lb.find(c) != std::string::npos && lo.find(c) == std::string::npos) ki += c;
+  const double* pA = arena + dA.offset;
+  const double* pB = arena + dB.offset;
+  double* pO = arena + dO.offset;
+  const double* pC0 = op.c0 >= 0 ? arena + g.t[op.c0].offset : nullptr;
+
+  // scalar output: deterministic dot product
+  if (lo.empty()) {
+    std::string kord = filter(la, ki);
+    View vb = fuse(lb, dB, kord);
+    P.dot = true;
+    int64_t n = dA.size();
+    if (!(vb.ok && (vb.stride == 1 || n == 1))) {
+      P.packB = true;
+      P.pb = pack_args(dB, lb, kord, pB, scratch);
+      P.scratch = n;
+    }
+    P.g.K = n;
+    P.g.alpha = op.alpha;
+    P.g.beta = op.beta;
+    P.g.A = pA;
+    P.g.B = P.packB ? scratch : pB;
+    P.g.Cin = pC0;
+    P.g.C = pO;
+    return P;
+  }
+
+  // choose fused orders; candidates from each operand's memory order
+  std::vector<std::string> mcand = {filter(lo, mi), filter(la, mi)};
+  std::vector<std::string> ncand = {filter(lo, ni), filter(lb, ni)};
+  std::vector<std::string> kcand = {filter(la, ki), filter(lb, ki)};
+  std::string bord = filter(lo, bat);
+  int64_t best = -1;
+  std::string bm, bn, bk;
+  for (auto& m : mcand)
+    for (auto& n : ncand)
+      for (auto& k : kcand) {
+        int64_t cost = 0;
+        auto okA = fuse(la, dA, m).ok && fuse(la, dA, k).ok && fuse(la, dA, bord).ok;
+        auto okB = fuse(lb, dB, k).ok && fuse(lb, dB, n).ok && fuse(lb, dB, bord).ok;
+        auto okC = fuse(lo, dO, m).ok && fuse(lo, dO, n).ok && fuse(lo, dO, bord).ok;
+        if (!okA) cost += dA.size();
+        if (!okB) cost += dB.size();
+        if (!okC) cost += 2 * dO.size();
+        if (best < 0 || cost < best) {
+          best = cost;
+          bm = m;
+          bn = n;
+          bk = k;
+        }
+      }
+  int64_t M = 1, N = 1, K = 1, Bt = 1;
+  for (char c : bm) M *= dO.dim[lo.find(c)];
+  for (char c : bn) N *= dO.dim[lo.find(c)];
+  for (char c : bk) K *= dA.dim[la.find(c)];
+  for (char c : bord) Bt *= dO.dim[lo.find(c)];
+  GemmArgs& G = P.g;
+  G.M = M;
+  G.N = N;
+  G.K = K;
+  G.batch = Bt;
+  G.alpha = op.alpha;
+  G.beta = op.beta;
+  int64_t sc = 0;
+  // A
+  {
+    View vm = fuse(la, dA, bm), vk = fuse(la, dA, bk), vb = fuse(la, dA, bord);
+    if (vm.ok && vk.ok && vb.ok) {
+      G.A = pA;
+      G.sAm = vm.stride;
+      G.sAk = vk.stride;
+      G.sAb = vb.stride;
+    } else {
+      P.packA = true;
+      P.pa = pack_args(dA, la, bord + bm + bk, pA, scratch + sc);
+      G.A = scratch + sc;
+      G.sAk = 1;
+      G.sAm = K;
+      G.sAb = M * K;
+      sc += dA.size();
+    }
+  }
+  // B
+  {
+    View vk = fuse(lb, dB, bk), vn = fuse(lb, dB, bn), vb = fuse(lb, dB, bord);
+    if (vk.ok && vn.ok && vb.ok) {
+      G.B = pB;
+      G.sBk = vk.stride;
+      G.sBn = vn.stride;
+      G.sBb = vb.stride;
+    } else {
+      P.packB = true;
+      P.pb = pack_args(dB, lb, bord + bk + bn, pB, scratch + sc);
+      G.B = scratch + sc;
+      G.sBn = 1;
+      G.sBk = N;
+      G.sBb = K * N;
+      sc += dB.size();
+    }
+  }
+  // C
+  {
+    View vm = fuse(lo, dO, bm), vn = fuse(lo, dO, bn), vb = fuse(lo, dO, bord);
+    if (vm.ok && vn.ok && vb.ok) {
+      G.C = pO;
+      G.Cin = pC0;
+      G.sCm = vm.stride;
+      G.sCn = vn.stride;
+      G.sCb = vb.stride;
+    } else {
+      P.tmpC = true;
+      double* tmp = scratch + sc;
+      sc += dO.size();
+      G.C = tmp;
+      G.Cin = nullptr;
+      G.beta = 0.0;
+      G.sCn = 1;
+      G.sCm = N;
+      G.sCb = M * N;
+      // out[lo] = tmp[bord+bm+bn] + beta c0
+      std::string tl = bord + bm + bn;
+      PermArgs& p = P.pc;
+      p = PermArgs{};
+      p.nd = (int)lo.size();
+      p.nin = 1;
+      p.in[0] = tmp;
+      p.coef[0] = 1.0;
+      p.out = pO;
+      p.addend = pC0;
+      p.beta = op.beta;
+      std::vector<int64_t> tst(tl.size(), 1);
+      for (int i = (int)tl.size() - 2; i >= 0; --i) tst[i] = tst[i + 1] * dO.dim[lo.find(tl[i + 1])];
+      auto ost = row_major_strides(dO);
+      int64_t total = 1;
+      for (int i = 0; i < p.nd; ++i) {
+        p.dim[i] = dO.dim[i];
+        p.ostr[i] = ost[i];
+        p.istr[0][i] = tst[tl.find(lo[i])];
+        total *= dO.dim[i];
+      }
+      p.total = total;
+    }
+  }
+  // split-K when the output tiles cannot fill the chip and K is long
+  {
+    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * Bt;
+    const int64_t target = 1024;
+    if (Bt == 1 && K >= 512 && tiles < target) {
+      int64_t sp = std::min<int64_t>((target + tiles - 1) / tiles, K / 256);
+      sp = std::min<int64_t>(sp, 64);
+      if (sp > 1) {
+        int64_t kc = (K + sp - 1) / sp;
+        kc = (kc + BK - 1) / BK * BK;
+        sp = (K + kc - 1) / kc;
+        if (sp > 1) {
+          G.splits = sp;
+          G.kchunk = kc;
+          G.P = scratch + sc;
+          sc += sp * M * N;
+        }
+      }
+    }
+  }
+  P.scratch = sc;
+  return P;
+}
+
+int64_t Executor::plan_scratch(Graph& g) {
+  int64_t mx = 0;
+  for (auto& op : g.ops)
+    if (op.kind == OpKind::Contract) {
+      ContractPlan p = plan_contract(g, op, nullptr, nullptr);
+      mx = std::max(mx, p.scratch);
+    }
+  return mx;
+}
+
+void Executor::plan_all() {
+  plans_.assign(g_.ops.size(), ContractPlan{});
+  for (size_t k = 0; k < g_.ops.size(); ++k)
+    if (g_.ops[k].kind == OpKind::Contract) {
+      plans_[k] = plan_contract(g_, g_.ops[k], arena_, scratch_);
+      if (plans_[k].scratch > scratch_n_) throw std::runtime_error("scratch too small");
+    }
+}
+
+Executor::~Executor() {
+  for (auto& e : ev_) (void)hipEventDestroy(e);
+}
+
+void Executor::set_profile(bool on) {
+  if (on && ev_.empty()) {
+    ev_.resize(2 * 4096);
+    for (auto& e : ev_) check(hipEventCreate(&e), "event create");
+    ev_flops_.resize(4096);
+  }
+  if (!on) flush_profile();
+  prof_ = on;
+}
+
+void Executor::flush_profile() {
+  if (nev_ == 0) return;
+  check(hipEventSynchronize(ev_[2 * nev_ - 1]), "event sync");
+  for (size_t i = 0; i < nev_; ++i) {
+    float ms = 0;
+    check(hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]), "event elapsed");
+    gemm_ms += ms;
+    gemm_flops += ev_flops_[i];
+  }
+  gemm_launches += (int64_t)nev_;
+  nev_ = 0;
+}
+
+void Executor::timed_gemm(const GemmArgs& g, hipStream_t s) {
+  if (nev_ == ev_flops_.size()) flush_profile();
+  check(hipEventRecord(ev_[2 * nev_], s), "event record");
+  launch_gemm(g, s);
+  check(hipEventRecord(ev_[2 * nev_ + 1], s), "event record");
+  ev_flops_[nev_] = 2.0 * g.M * g.N * g.K * g.batch;
+  ++nev_;
+}
+
+double Executor::flops(const std::vector<int>& list) const {
+  double f = 0;
+  for (int k : list)
+    if (g_.ops[k].kind == OpKind::Contract) {
+      const ContractPlan& p = plans_[k];
+      if (p.dot)
+        f += 2.0 * p.g.K;
+      else
+        f += 2.0 * p.g.M * p.g.N * p.g.K * p.g.batch;
+    }
+  return f;
+}
+
+void Executor::run(const std::vector<int>& list, hipStream_t s) {
+  for (int k : list) run_op(k, s);
+}
+
+void Executor::run_op(int k, hipStream_t s) {
+  const Op& op = g_.ops[k];
+  switch (op.kind) {
+    case OpKind::Contract: {
+      const ContractPlan& p = plans_[k];
+      if (p.packA) launch_perm(p.pa, s);
+      if (p.packB) launch_perm(p.pb, s);
+      if (p.dot) {
+        launch_dot(p.g.A, p.g.B, p.g.K, p.g.alpha, p.g.Cin, p.g.beta, p.g.C, partials_, s);
+      } else {
+        if (prof_)
+          timed_gemm(p.g, s);
+        else
+          launch_gemm(p.g, s);
+        if (p.tmpC) launch_perm(p.pc, s);
+      }
+      break;
+    }
+    case OpKind::Lincomb: {
+      const TensorDesc& dO = g_.t[op.out];
+      auto ost = row_major_strides(dO);
+      size_t i0 = 0;
+      const double* prev = nullptr;
+      while (i0 < op.ins.size()) {
+        PermArgs p{};
+        p.nd = dO.nd;
+        int64_t total = 1;
+        for (int d = 0; d < dO.nd; ++d) {
+          p.dim[d] = dO.dim[d];
+          p.ostr[d] = ost[d];
+          total *= dO.dim[d];
+        }
+        if (dO.nd == 0) {
+          p.nd = 1;
+          p.dim[0] = 1;
+          p.ostr[0] = 0;
+        }
+        p.total = total;
+        p.out = ptr(op.out);
+        p.addend = prev;
+        p.beta = prev ? 1.0 : 0.0;
+        int cnt = 0;
+        for (; i0 < op.ins.size() && cnt < 4; ++i0, ++cnt) {
+          const TensorDesc& di = g_.t[op.ins[i0]];
+          auto ist = row_major_strides(di);
+          p.in[cnt] = ptr(op.ins[i0]);
+          p.coef[cnt] = op.coef[i0];
+          for (int d = 0; d < dO.nd; ++d) p.istr[cnt][d] = ist[op.lin[i0].find(op.lo[d])];
+          if (dO.nd == 0) p.istr[cnt][0] = 0;
+        }
+        p.nin = cnt;
+        launch_perm(p, s);
+        prev = p.out;
+      }
+      break;
+    }
+    case OpKind::Slice:
+    case OpKind::Embed: {
+      const TensorDesc& di = g_.t[op.a];
+      const TensorDesc& dO = g_.t[op.out];
+      auto ist = row_major_strides(di);
+      auto ost = row_major_strides(dO);
+      PermArgs p{};
+      p.nin = 1;
+      p.coef[0] = 1.0;
+      p.addend = nullptr;
+      if (op.kind == OpKind::Slice) {
+        int64_t base = 0;
+        for (int d = 0; d < di.nd; ++d) base += op.off[d] * ist[d];
+        p.nd = dO.nd;
+        for (int d = 0; d < dO.nd; ++d) {
+          p.dim[d] = dO.dim[d];
+          p.istr[0][d] = ist[d];
+          p.ostr[d] = ost[d];
+        }
+        p.in[0] = ptr(op.a) + base;
+        p.out = ptr(op.out);
+        p.total = dO.size();
+      } else {
+        launch_fill(ptr(op.out), dO.size(), 0.0, s);
+        int64_t base = 0;
+        for (int d = 0; d < dO.nd; ++d) base += op.off[d] * ost[d];
+        p.nd = di.nd;
+        for (int d = 0; d < di.nd; ++d) {
+          p.dim[d] = di.dim[d];
+          p.istr[0][d] = ist[d];
+          p.ostr[d] = ost[d];
+        }
+        p.in[0] = ptr(op.a);
+        p.out = ptr(op.out) + base;
+        p.total = di.size();
+      }
+      launch_perm(p, s);
+      break;
+    }
+  }
+}
+
+}  // namespace scc

@@ -1,0 +1,107 @@
+// GPU executor for contraction programs (ir.hpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ir.hpp"
+
+namespace scc {
+
+// C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] + beta * Cin[b][m][n]
+// with arbitrary element strides (one stride of each operand is normally 1).
+struct GemmArgs {
+  int64_t M, N, K, batch;
+  double alpha, beta;
+  const double* A;
+  int64_t sAb, sAm, sAk;
+  const double* B;
+  int64_t sBb, sBk, sBn;
+  const double* Cin;
+  double* C;
+  int64_t sCb, sCm, sCn;
+  // split-K: `splits` > 1 writes alpha * partial sums over K chunks of
+  // `kchunk` into P[split][m][n] (batch must be 1); a second pass adds them
+  // in a fixed order into C (+ beta Cin).
+  int64_t splits = 1, kchunk = 0;
+  double* P = nullptr;
+};
+
+// out[idx] = sum_i coef_i * in_i[idx . istr_i] + beta * addend[idx . ostr]
+// over the iteration shape `dim` (nd <= 6); out written at idx . ostr.
+struct PermArgs {
+  int nd;
+  int64_t dim[MAXD];
+  int nin;
+  const double* in[4];
+  int64_t istr[4][MAXD];
+  double coef[4];
+  double* out;
+  int64_t ostr[MAXD];
+  const double* addend;
+  double beta;
+  int64_t total;
+};
+
+void launch_gemm(const GemmArgs& a, hipStream_t s);
+void launch_perm(const PermArgs& a, hipStream_t s);
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+// out[0] = alpha * sum x[i] y[i] + beta * addend[0]  (deterministic order);
+// `partials` needs 1024 doubles.
+void launch_dot(const double* x, const double* y, int64_t n, double alpha, const double* addend,
+                double beta, double* out, double* partials, hipStream_t s);
+// y = a x + b y (elementwise)
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+// y[i] = x[i] / max(|d[i] - shift|, floor) * sign(d[i] - shift)
+void launch_precond(const double* x, const double* d, double shift, double floor_, double* y,
+                    int64_t n, hipStream_t s);
+// Symmetrise a doubles block in place: X[a,i,b,j] = (X[a,i,b,j] + X[b,j,a,i]) / 2
+void launch_sym_pairs(double* x, int64_t nov, hipStream_t s);
+// grad[k] = sum_p dh[k][p] D1[p] + sum_q dL[k][q] Z[q], k < ncoord
+void launch_deriv_contract(const double* dh, int64_t nh, const double* D1, const double* dL, int64_t nl,
+                           const double* Z, int ncoord, double* grad, double* partials, hipStream_t s);
+
+struct ContractPlan {
+  // operand packs: -1 = use directly
+  bool packA = false, packB = false, tmpC = false, dot = false;
+  GemmArgs g{};
+  PermArgs pa{}, pb{}, pc{};
+  int64_t scratch = 0;  // doubles of scratch needed
+};
+
+class Executor {
+ public:
+  Executor(Graph& g, double* arena, double* scratch, int64_t scratch_doubles, double* partials)
+      : g_(g), arena_(arena), scratch_(scratch), scratch_n_(scratch_doubles), partials_(partials) {}
+  // plan every op (call after Graph::finalize); returns max scratch needed
+  static int64_t plan_scratch(Graph& g);
+  void plan_all();
+  void run(const std::vector<int>& op_list, hipStream_t s);
+  double* ptr(int id) const { return arena_ + g_.t[id].offset; }
+  double flops(const std::vector<int>& op_list) const;
+  // GEMM kernel timing with HIP events (off by default)
+  void set_profile(bool on);
+  void flush_profile();
+  double gemm_ms = 0.0, gemm_flops = 0.0;
+  int64_t gemm_launches = 0;
+  ~Executor();
+
+ private:
+  Graph& g_;
+  double* arena_;
+  double* scratch_;
+  int64_t scratch_n_;
+  double* partials_;
+  std::vector<ContractPlan> plans_;
+  bool prof_ = false;
+  std::vector<hipEvent_t> ev_;
+  std::vector<double> ev_flops_;
+  size_t nev_ = 0;
+  void run_op(int k, hipStream_t s);
+  void timed_gemm(const GemmArgs& g, hipStream_t s);
+};
+
+ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* scratch);
+
+}  // namespace scc

@@ -1,0 +1,351 @@
+// Contraction-program graph, zero folding, and the JVP / VJP transforms.
+#include "ir.hpp"
+
+#include <algorithm>
+#include <stdexcept>
+
+namespace scc {
+
+Spec parse_spec(const std::string& s) {
+  Spec r;
+  auto arrow = s.find("->");
+  auto comma = s.find(',');
+  if (arrow == std::string::npos || comma == std::string::npos || comma > arrow)
+    throw std::runtime_error("bad contraction spec: " + s);
+  r.la = s.substr(0, comma);
+  r.lb = s.substr(comma + 1, arrow - comma - 1);
+  r.lo = s.substr(arrow + 2);
+  return r;
+}
+
+static void no_repeats(const std::string& l) {
+  for (size_t i = 0; i < l.size(); ++i)
+    for (size_t j = i + 1; j < l.size(); ++j)
+      if (l[i] == l[j]) throw std::runtime_error("repeated index in " + l);
+}
+
+int Graph::tensor(const std::vector<int64_t>& dims, const std::string& name) {
+  if (dims.size() > (size_t)MAXD) throw std::runtime_error("too many dims");
+  TensorDesc d;
+  d.nd = (int)dims.size();
+  for (size_t i = 0; i < dims.size(); ++i) d.dim[i] = dims[i];
+  d.name = name;
+  t.push_back(d);
+  return (int)t.size() - 1;
+}
+
+int Graph::zeros(const std::vector<int64_t>& dims) {
+  int id = tensor(dims, "0");
+  t[id].zero = true;
+  return id;
+}
+
+std::vector<int64_t> Graph::dims(int id) const {
+  return std::vector<int64_t>(t[id].dim.begin(), t[id].dim.begin() + t[id].nd);
+}
+
+void Graph::check_labels(const std::string& l, int id, const char* what) const {
+  if ((int)l.size() != t[id].nd)
+    throw std::runtime_error(std::string("label/rank mismatch in ") + what + " '" + l + "' for tensor " +
+                             t[id].name);
+  no_repeats(l);
+}
+
+int Graph::contract(const std::string& spec, int A, int B, double alpha, int c0, double beta) {
+  Spec s = parse_spec(spec);
+  check_labels(s.la, A, "contract A");
+  check_labels(s.lb, B, "contract B");
+  no_repeats(s.lo);
+  std::map<char, int64_t> sz;
+  auto reg = [&](const std::string& l, int id) {
+    for (size_t i = 0; i < l.size(); ++i) {
+      auto it = sz.find(l[i]);
+      if (it != sz.end() && it->second != t[id].dim[i])
+        throw std::runtime_error("dimension mismatch for index '" + std::string(1, l[i]) + "' in " + spec);
+      sz[l[i]] = t[id].dim[i];
+    }
+  };
+  reg(s.la, A);
+  reg(s.lb, B);
+  for (char c : s.la + s.lb + s.lo) {
+    int n = (s.la.find(c) != std::string::npos) + (s.lb.find(c) != std::string::npos) +
+            (s.lo.find(c) != std::string::npos);
+    if (n < 2) throw std::runtime_error("index '" + std::string(1, c) + "' appears once in " + spec);
+  }
+  std::vector<int64_t> od;
+  for (char c : s.lo) od.push_back(sz.at(c));
+  if (c0 >= 0) {
+    if (dims(c0) != od) throw std::runtime_error("addend shape mismatch in " + spec);
+  }
+  bool zero_prod = t[A].zero || t[B].zero || alpha == 0.0;
+  if (zero_prod) {
+    if (c0 >= 0 && !t[c0].zero && beta != 0.0) return beta == 1.0 ? c0 : scale(c0, beta);
+    return zeros(od);
+  }
+  if (c0 >= 0 && (t[c0].zero || beta == 0.0)) c0 = -1;
+  int out = tensor(od, "c");
+  Op op;
+  op.kind = OpKind::Contract;
+  op.out = out;
+  op.a = A;
+  op.b = B;
+  op.c0 = c0;
+  op.alpha = alpha;
+  op.beta = c0 >= 0 ? beta : 0.0;
+  op.la = s.la;
+  op.lb = s.lb;
+  op.lo = s.lo;
+  ops.push_back(op);
+  return out;
+}
+
+int Graph::lincomb(const std::string& lo, const std::vector<Term>& terms) {
+  no_repeats(lo);
+  std::vector<int64_t> od(lo.size(), -1);
+  std::vector<Term> keep;
+  for (const auto& tm : terms) {
+    check_labels(tm.labels, tm.id, "lincomb");
+    for (size_t i = 0; i < tm.labels.size(); ++i) {
+      auto p = lo.find(tm.labels[i]);
+      if (p == std::string::npos) throw std::runtime_error("lincomb label not in output");
+      if (od[p] >= 0 && od[p] != t[tm.id].dim[i]) throw std::runtime_error("lincomb dim mismatch");
+      od[p] = t[tm.id].dim[i];
+    }
+    if (!t[tm.id].zero && tm.coef != 0.0) keep.push_back(tm);
+  }
+  for (auto d : od)
+    if (d < 0) throw std::runtime_error("lincomb: undetermined output dim");
+  if (keep.empty()) return zeros(od);
+  if (keep.size() == 1 && keep[0].coef == 1.0 && keep[0].labels == lo) return keep[0].id;
+  int out = tensor(od, "l");
+  Op op;
+  op.kind = OpKind::Lincomb;
+  op.out = out;
+  op.lo = lo;
+  for (const auto& tm : keep) {
+    op.ins.push_back(tm.id);
+    op.coef.push_back(tm.coef);
+    op.lin.push_back(tm.labels);
+  }
+  ops.push_back(op);
+  return out;
+}
+
+static std::string default_labels(int nd) { return std::string("abcdef").substr(0, nd); }
+
+int Graph::add(int A, int B, double ca, double cb) {
+  std::string l = default_labels(t[A].nd);
+  return lincomb(l, {{ca, A, l}, {cb, B, l}});
+}
+
+int Graph::scale(int A, double c) {
+  std::string l = default_labels(t[A].nd);
+  return lincomb(l, {{c, A, l}});
+}
+
+int Graph::slice(int in, const std::vector<int64_t>& off, const std::vector<int64_t>& sizes) {
+  if ((int)off.size() != t[in].nd || sizes.size() != off.size()) throw std::runtime_error("slice rank");
+  for (size_t i = 0; i < off.size(); ++i)
+    if (off[i] < 0 || off[i] + sizes[i] > t[in].dim[i]) throw std::runtime_error("slice out of range");
+  if (t[in].zero) return zeros(sizes);
+  if (sizes == dims(in)) return in;
+  int out = tensor(sizes, "s");
+  Op op;
+  op.kind = OpKind::Slice;
+  op.out = out;
+  op.a = in;
+  for (size_t i = 0; i < off.size(); ++i) op.off[i] = off[i];
+  ops.push_back(op);
+  return out;
+}
+
+int Graph::embed(int in, const std::vector<int64_t>& off, const std::vector<int64_t>& outdims) {
+  if ((int)off.size() != t[in].nd || outdims.size() != off.size()) throw std::runtime_error("embed rank");
+  for (size_t i = 0; i < off.size(); ++i)
+    if (off[i] < 0 || off[i] + t[in].dim[i] > outdims[i]) throw std::runtime_error("embed out of range");
+  if (t[in].zero) return zeros(outdims);
+  if (outdims == dims(in)) return in;
+  int out = tensor(outdims, "e");
+  Op op;
+  op.kind = OpKind::Embed;
+  op.out = out;
+  op.a = in;
+  for (size_t i = 0; i < off.size(); ++i) op.off[i] = off[i];
+  ops.push_back(op);
+  return out;
+}
+
+std::vector<int> Graph::jvp(int begin, int end, const std::map<int, int>& seeds) {
+  std::vector<int> tan(t.size(), -1);
+  for (auto& kv : seeds)
+    if (!t[kv.second].zero) tan[kv.first] = kv.second;
+  auto T = [&](int id) { return (id >= 0 && id < (int)tan.size()) ? tan[id] : -1; };
+  for (int k = begin; k < end; ++k) {
+    const Op op = ops[k];  // copy: ops may reallocate
+    int res = -1;
+    switch (op.kind) {
+      case OpKind::Contract: {
+        std::string spec = op.la + "," + op.lb + "->" + op.lo;
+        int cur = -1;
+        if (op.c0 >= 0 && T(op.c0) >= 0) cur = op.beta == 1.0 ? T(op.c0) : scale(T(op.c0), op.beta);
+        if (T(op.a) >= 0) cur = contract(spec, T(op.a), op.b, op.alpha, cur, 1.0);
+        if (T(op.b) >= 0) cur = contract(spec, op.a, T(op.b), op.alpha, cur, 1.0);
+        res = cur;
+        break;
+      }
+      case OpKind::Lincomb: {
+        std::vector<Term> terms;
+        for (size_t i = 0; i < op.ins.size(); ++i)
+          if (T(op.ins[i]) >= 0) terms.push_back({op.coef[i], T(op.ins[i]), op.lin[i]});
+        if (!terms.empty()) res = lincomb(op.lo, terms);
+        break;
+      }
+      case OpKind::Slice:
+        if (T(op.a) >= 0) {
+          std::vector<int64_t> off(op.off.begin(), op.off.begin() + t[op.a].nd);
+          res = slice(T(op.a), off, dims(op.out));
+        }
+        break;
+      case OpKind::Embed:
+        if (T(op.a) >= 0) {
+          std::vector<int64_t> off(op.off.begin(), op.off.begin() + t[op.a].nd);
+          res = embed(T(op.a), off, dims(op.out));
+        }
+        break;
+    }
+    if (res >= 0 && t[res].zero) res = -1;
+    if (op.out < (int)tan.size()) tan[op.out] = res;
+  }
+  return tan;
+}
+
+std::map<int, int> Graph::vjp(int begin, int end, const std::map<int, int>& seeds,
+                              const std::vector<int>& wanted) {
+  const int nt = (int)t.size();
+  std::vector<char> dep(nt, 0);
+  for (int w : wanted) dep[w] = 1;
+  for (int k = begin; k < end; ++k) {
+    const Op& op = ops[k];
+    bool d = false;
+    if (op.kind == OpKind::Contract)
+      d = dep[op.a] || dep[op.b] || (op.c0 >= 0 && dep[op.c0]);
+    else if (op.kind == OpKind::Lincomb)
+      for (int i : op.ins) d = d || dep[i];
+    else
+      d = dep[op.a];
+    if (d) dep[op.out] = 1;
+  }
+  std::map<int, std::vector<int>> contrib;
+  for (auto& kv : seeds)
+    if (!t[kv.second].zero) contrib[kv.first].push_back(kv.second);
+  auto total = [&](int id) -> int {
+    auto it = contrib.find(id);
+    if (it == contrib.end() || it->second.empty()) return -1;
+    if (it->second.size() == 1) return it->second[0];
+    std::string l = default_labels(t[id].nd);
+    std::vector<Term> terms;
+    for (int c : it->second) terms.push_back({1.0, c, l});
+    int s = lincomb(l, terms);
+    it->second.assign(1, s);
+    return s;
+  };
+  for (int k = end - 1; k >= begin; --k) {
+    const Op op = ops[k];
+    if (!dep[op.out]) continue;
+    int g = total(op.out);
+    if (g < 0 || t[g].zero) continue;
+    switch (op.kind) {
+      case OpKind::Contract: {
+        if (dep[op.a]) {
+          int r = contract(op.lo + "," + op.lb + "->" + op.la, g, op.b, op.alpha);
+          if (!t[r].zero) contrib[op.a].push_back(r);
+        }
+        if (dep[op.b]) {
+          int r = contract(op.la + "," + op.lo + "->" + op.lb, op.a, g, op.alpha);
+          if (!t[r].zero) contrib[op.b].push_back(r);
+        }
+        if (op.c0 >= 0 && dep[op.c0]) contrib[op.c0].push_back(op.beta == 1.0 ? g : scale(g, op.beta));
+        break;
+      }
+      case OpKind::Lincomb:
+        for (size_t i = 0; i < op.ins.size(); ++i)
+          if (dep[op.ins[i]]) contrib[op.ins[i]].push_back(lincomb(op.lin[i], {{op.coef[i], g, op.lo}}));
+        break;
+      case OpKind::Slice:
+        if (dep[op.a]) {
+          std::vector<int64_t> off(op.off.begin(), op.off.begin() + t[op.a].nd);
+          contrib[op.a].push_back(embed(g, off, dims(op.a)));
+        }
+        break;
+      case OpKind::Embed:
+        if (dep[op.a]) {
+          std::vector<int64_t> off(op.off.begin(), op.off.begin() + t[op.a].nd);
+          contrib[op.a].push_back(slice(g, off, dims(op.a)));
+        }
+        break;
+    }
+  }
+  std::map<int, int> out;
+  for (int w : wanted) out[w] = total(w);
+  return out;
+}
+
+std::vector<int> Graph::needed_ops(const std::vector<int>& outputs, const std::set<int>& have) const {
+  std::vector<char> need(t.size(), 0);
+  for (int o : outputs)
+    if (o >= 0 && !have.count(o)) need[o] = 1;
+  std::vector<int> list;
+  for (int k = (int)ops.size() - 1; k >= 0; --k) {
+    const Op& op = ops[k];
+    if (!need[op.out]) continue;
+    list.push_back(k);
+    auto mark = [&](int id) {
+      if (id >= 0 && !have.count(id)) need[id] = 1;
+    };
+    if (op.kind == OpKind::Contract) {
+      mark(op.a);
+      mark(op.b);
+      mark(op.c0);
+    } else if (op.kind == OpKind::Lincomb) {
+      for (int i : op.ins) mark(i);
+    } else {
+      mark(op.a);
+    }
+  }
+  std::reverse(list.begin(), list.end());
+  return list;
+}
+
+std::vector<int> Graph::dependent_ops(const std::vector<int>& list, const std::set<int>& vars) const {
+  std::vector<char> dep(t.size(), 0);
+  for (int v : vars) dep[v] = 1;
+  std::vector<int> out;
+  for (int k : list) {
+    const Op& op = ops[k];
+    bool d = false;
+    if (op.kind == OpKind::Contract)
+      d = dep[op.a] || dep[op.b] || (op.c0 >= 0 && dep[op.c0]);
+    else if (op.kind == OpKind::Lincomb)
+      for (int i : op.ins) d = d || dep[i];
+    else
+      d = dep[op.a];
+    if (d) {
+      dep[op.out] = 1;
+      out.push_back(k);
+    }
+  }
+  return out;
+}
+
+int64_t Graph::finalize(int64_t align) {
+  int64_t pos = 0;
+  for (auto& d : t) {
+    if (d.zero) continue;
+    d.offset = pos;
+    int64_t s = d.size();
+    pos += (s + align - 1) / align * align;
+  }
+  return pos;
+}
+
+}  // namespace scc

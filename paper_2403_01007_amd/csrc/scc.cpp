@@ -1,0 +1,1244 @@
+// libscc: context, solvers and the C ABI (include/scc.h).
+//
+// Iteration control runs on the host; every vector operation, every
+// contraction and every reduction runs on the GPU.  Subspace problems (DIIS
+// coefficients, Davidson subspace eigenproblem, GMRES least squares) are a
+// few tens of numbers and are solved on the host in FP64.
+#include "../../include/scc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "exec.hpp"
+#include "model.hpp"
+#include "smalllinalg.hpp"
+
+using namespace scc;
+
+namespace {
+
+struct SccError : std::runtime_error {
+  int code;
+  SccError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hck(hipError_t e) {
+  if (e != hipSuccess) throw SccError(SCC_EDEVICE, std::string("hip: ") + hipGetErrorString(e));
+}
+
+constexpr int NDIIS = 8;
+constexpr int GMRES_M = 40;
+constexpr int64_t PARTIALS = 1 << 18;
+
+int64_t up(int64_t x, int64_t a = 32) { return (x + a - 1) / a * a; }
+
+struct Sizes {
+  int64_t nov, nvt, nst, nlag;
+  int maxsub;
+  int64_t pool;
+};
+
+Sizes sizes_for(const Dims& d) {
+  Sizes s;
+  s.nov = d.nov();
+  s.nvt = s.nov + s.nov * s.nov;
+  s.nst = 1 + s.nvt;
+  s.nlag = s.nvt + d.ns * (s.nst + 1) + d.npairs();
+  s.maxsub = std::max(20, 8 * d.ns + 8);
+  int64_t p = 0;
+  p += up(s.nvt);                       // D
+  p += 2 * d.ns * up(s.nst);            // R, L
+  p += 2 * NDIIS * up(s.nvt) + 3 * up(s.nvt);
+  p += 2 * s.maxsub * up(s.nvt) + 4 * (d.ns + 2) * up(s.nvt) + 2 * up(s.nvt);
+  p += (2 * GMRES_M + 4) * up(s.nlag);
+  p += (2 * GMRES_M + 4) * up(s.nov) + 2 * up(s.nov);
+  p += 64;
+  s.pool = p;
+  return s;
+}
+
+}  // namespace
+
+struct scc_ctx {
+  Model m;
+  Sizes sz{};
+  std::unique_ptr<Executor> ex;
+  hipStream_t s = nullptr;
+  double* arena = nullptr;
+  double* scratch = nullptr;
+  int64_t scratch_n = 0;
+  double* partials = nullptr;
+  double* pool = nullptr;
+  int64_t pool_used = 0;
+  scc_options opt{};
+  std::string err;
+  // persistent device vectors
+  double* D = nullptr;        // orbital-energy denominators [nov | nov^2]
+  std::vector<double*> R, Lv; // states [r0 | r1 | r2]
+  double* kbar = nullptr;
+  double* dsc = nullptr;      // device scalars
+  std::vector<double> eps;
+  bool have_h = false, have_ground = false, have_excited = false, have_mult = false;
+  double E0 = 0.0, enuc = 0.0;
+  std::vector<double> E, zeta;
+  int mult_kind = -1, mult_m = -1, mult_n = -1;
+  double flops = 0.0;
+
+  double* alloc(int64_t n) {
+    double* p = pool + pool_used;
+    pool_used += up(n);
+    if (pool_used > sz.pool) throw SccError(SCC_ENOMEM, "solver pool exhausted");
+    return p;
+  }
+  double* tp(int id) { return ex->ptr(id); }
+  bool zero(int id) const { return m.g.t[id].zero; }
+  void run(const std::vector<int>& l) {
+    ex->run(l, s);
+    flops += ex->flops(l);
+  }
+  void sync() {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) throw SccError(SCC_EDEVICE, std::string("hip: ") + hipGetErrorString(e));
+  }
+  void cp(double* dst, const double* src, int64_t n) {
+    if (n <= 0) return;
+    hipError_t e = hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) throw SccError(SCC_EDEVICE, "memcpy");
+  }
+  // copy tensor -> buffer (zeros for identically-zero tensors)
+  void get(int id, double* dst) {
+    int64_t n = m.g.t[id].size();
+    if (zero(id))
+      launch_fill(dst, n, 0.0, s);
+    else
+      cp(dst, tp(id), n);
+  }
+  void put(int id, const double* src) { cp(tp(id), src, m.g.t[id].size()); }
+  double host_scalar(const double* dp) {
+    double v = 0;
+    sync();
+    hipError_t e = hipMemcpy(&v, dp, sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) throw SccError(SCC_EDEVICE, "memcpy d2h");
+    return v;
+  }
+  double tensor_scalar(int id) { return zero(id) ? 0.0 : host_scalar(tp(id)); }
+  void set_scalar(int id, double v) { launch_fill(tp(id), 1, v, s); }
+  double dot(const double* x, const double* y, int64_t n) {
+    launch_dot(x, y, n, 1.0, nullptr, 0.0, dsc, partials, s);
+    return host_scalar(dsc);
+  }
+  void axpby(double a, const double* x, double b, double* y, int64_t n) { launch_axpby(a, x, b, y, n, s); }
+  void fill(double* p, int64_t n, double v) { launch_fill(p, n, v, s); }
+  // state <-> tensors
+  void put_state(const StateT& st, const double* v) {
+    put(st.r0, v);
+    put(st.r1, v + 1);
+    put(st.r2, v + 1 + sz.nov);
+  }
+  void get_state(const StateT& st, double* v) {
+    get(st.r0, v);
+    get(st.r1, v + 1);
+    get(st.r2, v + 1 + sz.nov);
+  }
+  void sym_doubles(double* x) { launch_sym_pairs(x, sz.nov, s); }
+  void log(const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+};
+
+void scc_ctx::log(const char* fmt, ...) {
+  if (!opt.verbose) return;
+  va_list ap;
+  va_start(ap, fmt);
+  vfprintf(stderr, fmt, ap);
+  va_end(ap);
+  fflush(stderr);
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// ground state: Jacobi steps with the orbital-energy preconditioner + DIIS
+// ---------------------------------------------------------------------------
+int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
+  Model& m = c->m;
+  const int64_t nvt = c->sz.nvt, nov = c->sz.nov;
+  int64_t mark = c->pool_used;
+  double* x = c->alloc(nvt);
+  double* r = c->alloc(nvt);
+  double* e = c->alloc(nvt);
+  std::vector<double*> X(NDIIS), Ev(NDIIS);
+  for (int i = 0; i < NDIIS; ++i) {
+    X[i] = c->alloc(nvt);
+    Ev[i] = c->alloc(nvt);
+  }
+  c->get(m.t1, x);
+  c->get(m.t2, x + nov);
+  int nh = 0, head = 0, it = 0;
+  std::vector<double> B(NDIIS * NDIIS, 0.0);
+  for (it = 0; it < maxit; ++it) {
+    c->put(m.t1, x);
+    c->put(m.t2, x + nov);
+    c->run(m.p_res);
+    c->get(m.res.O1, r);
+    c->get(m.res.O2, r + nov);
+    rn = std::sqrt(c->dot(r, r, nvt));
+    c->log("  ground it %3d  |Omega| %.3e\n", it, rn);
+    if (rn < tol) break;
+    launch_precond(r, c->D, 0.0, 1e-8, e, nvt, c->s);
+    int slot = head;
+    head = (head + 1) % NDIIS;
+    nh = std::min(nh + 1, NDIIS);
+    c->cp(X[slot], x, nvt);
+    c->axpby(-1.0, e, 1.0, X[slot], nvt);
+    c->cp(Ev[slot], e, nvt);
+    for (int i = 0; i < nh; ++i) {
+      double v = c->dot(Ev[slot], Ev[i], nvt);
+      B[slot * NDIIS + i] = B[i * NDIIS + slot] = v;
+    }
+    int n1 = nh + 1;
+    std::vector<double> A(n1 * n1, 0.0), b(n1, 0.0);
+    double scale = 0;
+    for (int i = 0; i < nh; ++i) scale = std::max(scale, B[i * NDIIS + i]);
+    if (scale <= 0) scale = 1;
+    for (int i = 0; i < nh; ++i) {
+      for (int j = 0; j < nh; ++j) A[i * n1 + j] = B[i * NDIIS + j] / scale;
+      A[i * n1 + nh] = A[nh * n1 + i] = -1.0;
+    }
+    b[nh] = -1.0;
+    if (!solve_linear(n1, A, b)) {
+      c->cp(x, X[slot], nvt);
+      continue;
+    }
+    c->fill(x, nvt, 0.0);
+    for (int i = 0; i < nh; ++i) c->axpby(b[i], X[i], 1.0, x, nvt);
+  }
+  c->put(m.t1, x);
+  c->put(m.t2, x + nov);
+  c->run(m.p_res);
+  c->pool_used = mark;
+  if (it >= maxit) return SCC_ENOCONV;
+  return SCC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// nonsymmetric Davidson on the excited-excited block (r0 = 0): right
+// eigenvectors of Hbar (left = false) or of Hbar^T (left = true)
+// ---------------------------------------------------------------------------
+void apply_block(scc_ctx* c, bool left, const double* v, double* w) {
+  Model& m = c->m;
+  const int64_t nov = c->sz.nov;
+  if (!left) {
+    c->set_scalar(m.vin.r0, 0.0);
+    c->put(m.vin.r1, v);
+    c->put(m.vin.r2, v + nov);
+    c->run(m.p_sig);
+    c->get(m.sig.s1, w);
+    c->get(m.sig.s2, w + nov);
+  } else {
+    c->set_scalar(m.lin.r0, 0.0);
+    c->put(m.lin.r1, v);
+    c->put(m.lin.r2, v + nov);
+    c->run(m.p_left);
+    c->get(m.lout.r1, w);
+    c->get(m.lout.r2, w + nov);
+  }
+  c->sym_doubles(w + nov);
+}
+
+int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>& guess, double tol, int maxit,
+             std::vector<double>& evals, std::vector<double*>& out, int& iters) {
+  const int64_t nvt = c->sz.nvt, nov = c->sz.nov;
+  const int maxsub = c->sz.maxsub;
+  int64_t mark = c->pool_used;
+  std::vector<double*> V(maxsub), W(maxsub);
+  for (int i = 0; i < maxsub; ++i) {
+    V[i] = c->alloc(nvt);
+    W[i] = c->alloc(nvt);
+  }
+  const int nx = nroots + 2;
+  std::vector<double*> Xr(nx), Xw(nx), Rs(nx);
+  for (int i = 0; i < nx; ++i) {
+    Xr[i] = c->alloc(nvt);
+    Xw[i] = c->alloc(nvt);
+    Rs[i] = c->alloc(nvt);
+  }
+  double* q = c->alloc(nvt);
+  int nv = 0;
+  auto add_vector = [&](double* src) -> bool {
+    double n0 = std::sqrt(c->dot(src, src, nvt));
+    if (!(n0 > 0)) return false;
+    c->axpby(0.0, src, 1.0 / n0, src, nvt);
+    // two passes of modified Gram-Schmidt against V
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < nv; ++j) {
+        double h = c->dot(V[j], src, nvt);
+        c->axpby(-h, V[j], 1.0, src, nvt);
+      }
+    double nr = std::sqrt(c->dot(src, src, nvt));
+    if (nr < 1e-8) return false;
+    c->cp(V[nv], src, nvt);
+    c->axpby(0.0, src, 1.0 / nr, V[nv], nvt);
+    ++nv;
+    return true;
+  };
+  if (!guess.empty()) {
+    for (auto* gv : guess) {
+      c->cp(q, gv + 1, nvt);
+      add_vector(q);
+    }
+  }
+  if (nv < nx) {
+    // unit vectors on the smallest singles denominators
+    std::vector<double> dh(nov);
+    hck(hipMemcpy(dh.data(), c->D, nov * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<int> idx(nov);
+    for (int64_t i = 0; i < nov; ++i) idx[i] = (int)i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return dh[a] < dh[b]; });
+    for (int64_t k = 0; k < nov && nv < nx; ++k) {
+      c->fill(q, nvt, 0.0);
+      launch_fill(q + idx[k], 1, 1.0, c->s);
+      add_vector(q);
+    }
+  }
+  std::vector<double> G(maxsub * maxsub, 0.0);
+  int nw = 0, ng = 0;
+  iters = 0;
+  for (int it = 0; it < maxit; ++it) {
+    iters = it + 1;
+    for (; nw < nv; ++nw) apply_block(c, left, V[nw], W[nw]);
+    for (int i = 0; i < nv; ++i)
+      for (int j = 0; j < nv; ++j)
+        if (i >= ng || j >= ng) G[i * maxsub + j] = c->dot(V[i], W[j], nvt);
+    ng = nv;
+    std::vector<double> Gs(nv * nv);
+    for (int i = 0; i < nv; ++i)
+      for (int j = 0; j < nv; ++j) Gs[i * nv + j] = G[i * maxsub + j];
+    std::vector<cplx> w, Y;
+    if (!eig_nonsym(nv, Gs, w, Y)) throw SccError(SCC_ENOCONV, "subspace eigensolver failed");
+    std::vector<int> ord(nv);
+    for (int i = 0; i < nv; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
+    double maxres = 0;
+    std::vector<double> th(nroots);
+    std::vector<char> conv(nroots, 0);
+    for (int k = 0; k < nroots; ++k) {
+      int col = ord[k];
+      th[k] = w[col].real();
+      // a complex-conjugate Ritz pair contributes Re(y) and Im(y)
+      const bool cplx_pair = std::fabs(w[col].imag()) > 1e-10 * std::max(1.0, std::fabs(w[col].real()));
+      const bool use_imag = cplx_pair && w[col].imag() < 0;
+      std::vector<double> y(nv);
+      double yn = 0;
+      for (int j = 0; j < nv; ++j) {
+        y[j] = use_imag ? Y[j * nv + col].imag() : Y[j * nv + col].real();
+        yn += y[j] * y[j];
+      }
+      yn = std::sqrt(yn);
+      c->fill(Xr[k], nvt, 0.0);
+      c->fill(Xw[k], nvt, 0.0);
+      for (int j = 0; j < nv; ++j) {
+        c->axpby(y[j] / yn, V[j], 1.0, Xr[k], nvt);
+        c->axpby(y[j] / yn, W[j], 1.0, Xw[k], nvt);
+      }
+      c->cp(Rs[k], Xw[k], nvt);
+      c->axpby(-th[k], Xr[k], 1.0, Rs[k], nvt);
+      double rn = std::sqrt(c->dot(Rs[k], Rs[k], nvt));
+      maxres = std::max(maxres, rn);
+      conv[k] = rn < tol;
+      if (cplx_pair) conv[k] = 0;
+    }
+    c->log("  %s davidson it %3d  nv %2d  max|r| %.3e  theta0 %.10f\n", left ? "left " : "right", it, nv, maxres,
+           th[0]);
+    if (maxres < tol) {
+      evals = th;
+      for (int k = 0; k < nroots; ++k) c->cp(out[k], Xr[k], nvt);
+      c->pool_used = mark;
+      return SCC_OK;
+    }
+    int nnew = 0;
+    for (int k = 0; k < nroots; ++k)
+      if (!conv[k]) ++nnew;
+    if (nv + nnew > maxsub) {
+      // collapse onto the current Ritz vectors (orthonormalised)
+      nv = 0;
+      for (int k = 0; k < nroots; ++k) {
+        for (int j = 0; j < nv; ++j) {
+          double h = c->dot(V[j], Xr[k], nvt);
+          c->axpby(-h, V[j], 1.0, Xr[k], nvt);
+          c->axpby(-h, W[j], 1.0, Xw[k], nvt);
+        }
+        double nr = std::sqrt(c->dot(Xr[k], Xr[k], nvt));
+        c->cp(V[nv], Xr[k], nvt);
+        c->axpby(0.0, Xr[k], 1.0 / nr, V[nv], nvt);
+        c->cp(W[nv], Xw[k], nvt);
+        c->axpby(0.0, Xw[k], 1.0 / nr, W[nv], nvt);
+        ++nv;
+      }
+      nw = nv;
+      ng = 0;
+    }
+    for (int k = 0; k < nroots; ++k) {
+      if (conv[k]) continue;
+      launch_precond(Rs[k], c->D, th[k], 1e-3, q, nvt, c->s);
+      c->sym_doubles(q + nov);
+      if (nv < maxsub) add_vector(q);
+    }
+  }
+  c->pool_used = mark;
+  return SCC_ENOCONV;
+}
+
+// ---------------------------------------------------------------------------
+// excited states with normalisation O_kk = 1, L.R = 1 and phase convention
+// ---------------------------------------------------------------------------
+double state_overlap(scc_ctx* c, const double* a, const double* b) {
+  Model& m = c->m;
+  c->put_state(m.oa, a);
+  c->put_state(m.ob, b);
+  c->run(m.p_ovl);
+  return c->tensor_scalar(m.ovl);
+}
+
+int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& iters) {
+  Model& m = c->m;
+  const int ns = c->m.d.ns;
+  const int64_t nvt = c->sz.nvt, nov = c->sz.nov, nst = c->sz.nst;
+  double rn = 0;
+  int rc = ground_solve(c, tol, maxit, rn);
+  if (rc) return rc;
+  c->E0 = c->tensor_scalar(m.res.E);
+  c->run(m.p_sig_pre);
+  std::vector<const double*> gr, gl;
+  if (warm)
+    for (int k = 0; k < ns; ++k) {
+      gr.push_back(c->R[k]);
+      gl.push_back(c->Lv[k]);
+    }
+  int64_t mark = c->pool_used;
+  std::vector<double*> outR(ns), outL(ns);
+  for (int k = 0; k < ns; ++k) {
+    outR[k] = c->alloc(nst);
+    outL[k] = c->alloc(nst);
+  }
+  std::vector<double*> oR(ns), oL(ns);
+  for (int k = 0; k < ns; ++k) {
+    oR[k] = outR[k] + 1;
+    oL[k] = outL[k] + 1;
+  }
+  std::vector<double> ER, EL;
+  int itR = 0, itL = 0;
+  rc = davidson(c, false, ns, gr, tol, maxit, ER, oR, itR);
+  if (rc) return rc;
+  rc = davidson(c, true, ns, gl, tol, maxit, EL, oL, itL);
+  if (rc) return rc;
+  iters += itR + itL;
+  c->E.assign(ns, 0.0);
+  for (int k = 0; k < ns; ++k) {
+    if (std::fabs(ER[k] - EL[k]) > 1e-6 * std::max(1.0, std::fabs(ER[k])))
+      throw SccError(SCC_ENOCONV, "left and right excitation energies differ");
+    c->E[k] = ER[k];
+    double om = ER[k] - c->E0;
+    if (std::fabs(om) < 1e-10) throw SccError(SCC_ESINGULAR, "excitation energy ~ 0");
+    // R0 = eta.R / omega from the reference row of calHbar
+    c->fill(outR[k], 1, 0.0);
+    c->put_state(m.vin, outR[k]);
+    c->run(m.p_sig);
+    double etaR = c->tensor_scalar(m.sig.s0);
+    launch_fill(outR[k], 1, etaR / om, c->s);
+    // O_kk = 1
+    double okk = state_overlap(c, outR[k], outR[k]);
+    c->axpby(0.0, outR[k], 1.0 / std::sqrt(okk), outR[k], nst);
+    // phase
+    if (warm) {
+      double ov = c->dot(c->Lv[k], outR[k], nst);
+      if (ov < 0) c->axpby(0.0, outR[k], -1.0, outR[k], nst);
+    } else {
+      std::vector<double> r1(nov);
+      c->sync();
+      hck(hipMemcpy(r1.data(), outR[k] + 1, nov * sizeof(double), hipMemcpyDeviceToHost));
+      int64_t im = 0;
+      for (int64_t i = 1; i < nov; ++i)
+        if (std::fabs(r1[i]) > std::fabs(r1[im])) im = i;
+      if (r1[im] < 0) c->axpby(0.0, outR[k], -1.0, outR[k], nst);
+    }
+    // L0 = 0, L.R = 1
+    c->fill(outL[k], 1, 0.0);
+    double lr = c->dot(outL[k], outR[k], nst);
+    c->axpby(0.0, outL[k], 1.0 / lr, outL[k], nst);
+  }
+  for (int k = 0; k < ns; ++k) {
+    c->cp(c->R[k], outR[k], nst);
+    c->cp(c->Lv[k], outL[k], nst);
+  }
+  c->pool_used = mark;
+  (void)nvt;
+  return SCC_OK;
+}
+
+void set_scc_inputs(scc_ctx* c, const std::vector<double>& zeta, bool states) {
+  Model& m = c->m;
+  for (size_t p = 0; p < m.zeta.size(); ++p) c->set_scalar(m.zeta[p], p < zeta.size() ? zeta[p] : 0.0);
+  if (states)
+    for (int k = 0; k < m.d.ns; ++k) c->put_state(m.xs[k], c->R[k]);
+}
+
+std::vector<double> pair_overlaps(scc_ctx* c) {
+  std::vector<double> O;
+  const int ns = c->m.d.ns;
+  for (int k = 0; k < ns; ++k)
+    for (int l = k + 1; l < ns; ++l) O.push_back(state_overlap(c, c->R[k], c->R[l]));
+  return O;
+}
+
+int excited_solve(scc_ctx* c, scc_info* info) {
+  const int ns = c->m.d.ns, np = c->m.d.npairs();
+  const double tol = c->opt.tol_residual;
+  const int maxit = c->opt.max_iter;
+  int iters = 0;
+  c->zeta.assign(np, 0.0);
+  set_scc_inputs(c, c->zeta, false);
+  int rc = excited_at_fixed_zeta(c, tol, maxit, false, iters);
+  if (rc) return rc;
+  const bool use_scc = c->opt.scc && c->m.d.o >= 2 && np > 0;
+  if (use_scc) {
+    const int64_t nst = c->sz.nst;
+    int64_t mark = c->pool_used;
+    std::vector<double*> prev(ns);
+    for (int k = 0; k < ns; ++k) prev[k] = c->alloc(nst);
+    std::vector<double> Jz;
+    std::vector<double> z = c->zeta, Oprev, zprev;
+    bool conv = false;
+    for (int it = 0; it < c->opt.max_iter && !conv; ++it) {
+      for (int k = 0; k < ns; ++k) c->cp(prev[k], c->R[k], nst);
+      set_scc_inputs(c, z, true);
+      rc = excited_at_fixed_zeta(c, tol, maxit, true, iters);
+      if (rc) return rc;
+      std::vector<double> O = pair_overlaps(c);
+      double dR = 0, omax = 0;
+      for (int k = 0; k < ns; ++k) {
+        double* dif = c->alloc(nst);
+        c->cp(dif, c->R[k], nst);
+        c->axpby(-1.0, prev[k], 1.0, dif, nst);
+        dR = std::max(dR, std::sqrt(c->dot(dif, dif, nst)));
+        c->pool_used -= up(nst);
+      }
+      for (double x : O) omax = std::max(omax, std::fabs(x));
+      c->log(" scc it %2d  max|O| %.3e  |dR| %.3e  zeta0 %.8f\n", it, omax, dR, z[0]);
+      if (omax < c->opt.tol_overlap && dR < 10 * tol) {
+        conv = true;
+        break;
+      }
+      if (Jz.empty()) {
+        // finite-difference Jacobian dO/dzeta with the X3 states held fixed
+        Jz.assign(np * np, 0.0);
+        const double h = 1e-5;
+        std::vector<double*> keepR(ns), keepL(ns);
+        for (int k = 0; k < ns; ++k) {
+          keepR[k] = c->alloc(nst);
+          keepL[k] = c->alloc(nst);
+          c->cp(keepR[k], c->R[k], nst);
+          c->cp(keepL[k], c->Lv[k], nst);
+        }
+        for (int p = 0; p < np; ++p) {
+          std::vector<double> zp = z;
+          zp[p] += h;
+          set_scc_inputs(c, zp, false);
+          rc = excited_at_fixed_zeta(c, tol, maxit, true, iters);
+          if (rc) return rc;
+          std::vector<double> Op = pair_overlaps(c);
+          for (int q = 0; q < np; ++q) Jz[q * np + p] = (Op[q] - O[q]) / h;
+          for (int k = 0; k < ns; ++k) {
+            c->cp(c->R[k], keepR[k], nst);
+            c->cp(c->Lv[k], keepL[k], nst);
+          }
+        }
+        c->pool_used -= 2 * ns * up(nst);
+      } else if (!Oprev.empty()) {
+        // Broyden update of the Jacobian
+        std::vector<double> dz(np), dO(np);
+        double dzz = 0;
+        for (int p = 0; p < np; ++p) {
+          dz[p] = z[p] - zprev[p];
+          dO[p] = O[p] - Oprev[p];
+          dzz += dz[p] * dz[p];
+        }
+        if (dzz > 0)
+          for (int q = 0; q < np; ++q) {
+            double jd = 0;
+            for (int p = 0; p < np; ++p) jd += Jz[q * np + p] * dz[p];
+            for (int p = 0; p < np; ++p) Jz[q * np + p] += (dO[q] - jd) * dz[p] / dzz;
+          }
+      }
+      std::vector<double> step = O;
+      if (!solve_linear(np, Jz, step)) throw SccError(SCC_ESINGULAR, "zeta Jacobian singular");
+      Oprev = O;
+      zprev = z;
+      for (int p = 0; p < np; ++p) z[p] -= step[p];
+    }
+    c->pool_used = mark;
+    c->zeta = z;
+    if (!conv) return SCC_ENOCONV;
+  }
+  if (info) {
+    info->iterations = iters;
+    info->converged = 1;
+  }
+  return SCC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES (right-preconditioned, restarted)
+// ---------------------------------------------------------------------------
+using LinOp = std::function<void(const double*, double*)>;
+
+int gmres(scc_ctx* c, int64_t n, const LinOp& A, const LinOp& Minv, const double* b, double* x, double tol,
+          int maxit, int& iters, double& relres) {
+  int64_t mark = c->pool_used;
+  std::vector<double*> V(GMRES_M + 1), Z(GMRES_M);
+  for (int i = 0; i <= GMRES_M; ++i) V[i] = c->alloc(n);
+  for (int i = 0; i < GMRES_M; ++i) Z[i] = c->alloc(n);
+  double* w = c->alloc(n);
+  double bn = std::sqrt(c->dot(b, b, n));
+  if (bn == 0) {
+    c->fill(x, n, 0.0);
+    c->pool_used = mark;
+    relres = 0;
+    return SCC_OK;
+  }
+  iters = 0;
+  for (int outer = 0; outer < maxit; ++outer) {
+    // r = b - A x
+    A(x, w);
+    c->cp(V[0], b, n);
+    c->axpby(-1.0, w, 1.0, V[0], n);
+    double beta = std::sqrt(c->dot(V[0], V[0], n));
+    relres = beta / bn;
+    c->log("  gmres restart %d  rel. residual %.3e\n", outer, relres);
+    if (relres < tol) {
+      c->pool_used = mark;
+      return SCC_OK;
+    }
+    c->axpby(0.0, V[0], 1.0 / beta, V[0], n);
+    std::vector<double> H((GMRES_M + 1) * GMRES_M, 0.0), cs(GMRES_M), sn(GMRES_M), gv(GMRES_M + 1, 0.0);
+    gv[0] = beta;
+    int j = 0;
+    for (; j < GMRES_M; ++j) {
+      ++iters;
+      Minv(V[j], Z[j]);
+      A(Z[j], w);
+      for (int i = 0; i <= j; ++i) {
+        double h = c->dot(V[i], w, n);
+        H[i * GMRES_M + j] = h;
+        c->axpby(-h, V[i], 1.0, w, n);
+      }
+      // second Gram-Schmidt pass for stability
+      for (int i = 0; i <= j; ++i) {
+        double h = c->dot(V[i], w, n);
+        H[i * GMRES_M + j] += h;
+        c->axpby(-h, V[i], 1.0, w, n);
+      }
+      double hn = std::sqrt(c->dot(w, w, n));
+      H[(j + 1) * GMRES_M + j] = hn;
+      if (hn > 0) {
+        c->cp(V[j + 1], w, n);
+        c->axpby(0.0, w, 1.0 / hn, V[j + 1], n);
+      }
+      for (int i = 0; i < j; ++i) {
+        double a = H[i * GMRES_M + j], bb = H[(i + 1) * GMRES_M + j];
+        H[i * GMRES_M + j] = cs[i] * a + sn[i] * bb;
+        H[(i + 1) * GMRES_M + j] = -sn[i] * a + cs[i] * bb;
+      }
+      double a = H[j * GMRES_M + j], bb = H[(j + 1) * GMRES_M + j];
+      double r = std::sqrt(a * a + bb * bb);
+      cs[j] = r == 0 ? 1.0 : a / r;
+      sn[j] = r == 0 ? 0.0 : bb / r;
+      H[j * GMRES_M + j] = r;
+      H[(j + 1) * GMRES_M + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      if (std::fabs(gv[j + 1]) / bn < 0.3 * tol || hn == 0) {
+        ++j;
+        break;
+      }
+    }
+    int k = std::min(j, GMRES_M);
+    std::vector<double> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      double s = gv[i];
+      for (int l = i + 1; l < k; ++l) s -= H[i * GMRES_M + l] * y[l];
+      y[i] = s / H[i * GMRES_M + i];
+    }
+    for (int i = 0; i < k; ++i) c->axpby(y[i], Z[i], 1.0, x, n);
+  }
+  c->pool_used = mark;
+  return SCC_ENOCONV;
+}
+
+// ---------------------------------------------------------------------------
+// Lagrangian: parameters, multipliers, targets
+// ---------------------------------------------------------------------------
+struct Seg {
+  int mult;   // multiplier tensor (cotangent input)
+  int adj;    // adjoint output tensor (parameter row)
+  int64_t n;
+  int kind;   // 0: t block, 1+k: state k block, -1: E / zeta
+  int comp;   // 0 scalar, 1 singles, 2 doubles
+};
+
+std::vector<Seg> lag_segments(scc_ctx* c) {
+  Model& m = c->m;
+  const int64_t nov = c->sz.nov;
+  std::vector<Seg> s;
+  s.push_back({m.m1, m.a_t1, nov, 0, 1});
+  s.push_back({m.m2, m.a_t2, nov * nov, 0, 2});
+  for (int k = 0; k < m.d.ns; ++k) {
+    s.push_back({m.mk[k].s0, m.a_r[k].r0, 1, 1 + k, 0});
+    s.push_back({m.mk[k].s1, m.a_r[k].r1, nov, 1 + k, 1});
+    s.push_back({m.mk[k].s2, m.a_r[k].r2, nov * nov, 1 + k, 2});
+    s.push_back({m.mN[k], m.a_E[k], 1, -1, 0});
+  }
+  for (int p = 0; p < m.d.npairs(); ++p) s.push_back({m.mO[p], m.a_z[p], 1, -1, 0});
+  return s;
+}
+
+void set_lagrangian_point(scc_ctx* c) {
+  Model& m = c->m;
+  const int64_t nov = c->sz.nov;
+  const int ns = m.d.ns;
+  double* tmp = c->alloc(c->sz.nvt);
+  c->get(m.t1, tmp);
+  c->get(m.t2, tmp + nov);
+  c->put(m.pt1, tmp);
+  c->put(m.pt2, tmp + nov);
+  c->put(m.nac_t1c, tmp);
+  c->put(m.nac_t2c, tmp + nov);
+  c->pool_used -= up(c->sz.nvt);
+  for (int p = 0; p < m.d.npairs(); ++p) c->set_scalar(m.pz[p], c->zeta[p]);
+  for (int k = 0; k < ns; ++k) {
+    c->put_state(m.pr[k], c->R[k]);
+    c->set_scalar(m.pE[k], c->E[k]);
+    c->put_state(m.lam[k], c->Lv[k]);
+  }
+  c->fill(c->tp(m.mF), nov, 0.0);
+  c->run(m.p_lag_pre);
+}
+
+int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
+  Model& m = c->m;
+  const int ns = m.d.ns;
+  const int64_t nov = c->sz.nov, n = c->sz.nlag;
+  set_lagrangian_point(c);
+  auto segs = lag_segments(c);
+  int64_t mark = c->pool_used;
+  double* b = c->alloc(n);
+  double* x = c->alloc(n);
+  c->fill(b, n, 0.0);
+  c->fill(x, n, 0.0);
+  // right-hand side b = -dTarget/dlambda (parameter layout)
+  int64_t off = 0;
+  std::vector<int64_t> offs;
+  for (auto& sg : segs) {
+    offs.push_back(off);
+    off += sg.n;
+  }
+  if (kind == 0) {
+    // gradient of E_n: unit vector on the E_n parameter
+    int idx = 2 + 4 * nn + 3;
+    launch_fill(b + offs[idx], 1, -1.0, c->s);
+  } else {
+    c->put_state(m.nac_l, c->Lv[mm]);
+    c->run(m.p_nac[nn]);
+    c->get(m.a_nac_t1[nn], b + offs[0]);
+    c->get(m.a_nac_t2[nn], b + offs[1]);
+    int base = 2 + 4 * nn;
+    c->get(m.a_nac_r[nn].r0, b + offs[base]);
+    c->get(m.a_nac_r[nn].r1, b + offs[base + 1]);
+    c->get(m.a_nac_r[nn].r2, b + offs[base + 2]);
+    c->axpby(0.0, b, -1.0, b, n);
+  }
+  // preconditioner: orbital-energy differences on the amplitude blocks
+  double* dzero = c->dsc + 8;
+  c->fill(dzero, 1, 0.0);
+  auto prec = [&](const double* in, double* out) {
+    for (size_t i = 0; i < segs.size(); ++i) {
+      const Seg& sg = segs[i];
+      if (sg.kind < 0) {
+        c->cp(out + offs[i], in + offs[i], sg.n);
+        continue;
+      }
+      double shift = sg.kind == 0 ? 0.0 : (c->E[sg.kind - 1] - c->E0);
+      const double* Dseg = sg.comp == 0 ? dzero : (sg.comp == 1 ? c->D : c->D + nov);
+      launch_precond(in + offs[i], Dseg, shift, 0.05, out + offs[i], sg.n, c->s);
+    }
+  };
+  auto apply = [&](const double* in, double* out) {
+    for (size_t i = 0; i < segs.size(); ++i) c->put(segs[i].mult, in + offs[i]);
+    c->run(m.p_lag);
+    for (size_t i = 0; i < segs.size(); ++i) {
+      c->get(segs[i].adj, out + offs[i]);
+      if (segs[i].comp == 2) c->sym_doubles(out + offs[i]);
+    }
+  };
+  int iters = 0;
+  double rel = 0;
+  int rc = gmres(c, n, apply, prec, b, x, c->opt.tol_residual, c->opt.max_iter, iters, rel);
+  if (rc) {
+    c->pool_used = mark;
+    return rc;
+  }
+  // leave the multipliers in their tensors
+  for (size_t i = 0; i < segs.size(); ++i) c->put(segs[i].mult, x + offs[i]);
+  // orbital multipliers: A_HF^T kbar = -(eta_kappa + dTarget/dkappa)
+  c->fill(c->tp(m.mF), nov, 0.0);
+  c->run(m.p_kappa);
+  double* rhs = c->alloc(nov);
+  c->get(m.a_kappa, rhs);
+  if (kind == 1) {
+    // coupling: dO_mn/dkappa_ai = -(d_ai - d_ia) with d = d(calL_m, calR_n)
+    c->run(m.p_sig_pre);
+    c->put_state(m.vin, c->R[nn]);
+    c->put_state(m.lin, c->Lv[mm]);
+    c->run(m.p_dens);
+    std::vector<double> dh((size_t)m.d.n * m.d.n);
+    c->sync();
+    if (!c->zero(m.dens_hk)) hck(hipMemcpy(dh.data(), c->tp(m.dens_hk), dh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> ck(nov);
+    const int o = m.d.o, v = m.d.v, N = m.d.n;
+    for (int a = 0; a < v; ++a)
+      for (int i = 0; i < o; ++i) ck[a * o + i] = -(dh[(o + a) * N + i] - dh[i * N + o + a]);
+    double* dck = c->alloc(nov);
+    hck(hipMemcpy(dck, ck.data(), nov * sizeof(double), hipMemcpyHostToDevice));
+    c->axpby(1.0, dck, 1.0, rhs, nov);
+  }
+  c->axpby(0.0, rhs, -1.0, rhs, nov);
+  auto applyF = [&](const double* in, double* out) {
+    c->put(m.mF, in);
+    c->run(m.p_fk);
+    c->get(m.fk_adj, out);
+  };
+  double* Dk = c->alloc(nov);
+  c->cp(Dk, c->D, nov);
+  auto precF = [&](const double* in, double* out) { launch_precond(in, Dk, 0.0, 1e-3, out, nov, c->s); };
+  c->fill(c->kbar, nov, 0.0);
+  int itk = 0;
+  double relk = 0;
+  rc = gmres(c, nov, applyF, precF, rhs, c->kbar, c->opt.tol_residual, c->opt.max_iter, itk, relk);
+  c->put(m.mF, c->kbar);
+  c->pool_used = mark;
+  if (rc) return rc;
+  c->have_mult = true;
+  c->mult_kind = kind;
+  c->mult_m = mm;
+  c->mult_n = nn;
+  if (info) {
+    info->iterations = iters + itk;
+    info->residual = std::max(rel, relk);
+    info->converged = 1;
+  }
+  (void)ns;
+  return SCC_OK;
+}
+
+int integral_adjoints(scc_ctx* c) {
+  Model& m = c->m;
+  c->put(m.mF, c->kbar);
+  c->run(m.p_integral);
+  return SCC_OK;
+}
+
+template <class F>
+int guarded(scc_ctx* c, scc_info* info, F&& f) {
+  auto t0 = std::chrono::steady_clock::now();
+  double f0 = c ? c->flops : 0;
+  int rc;
+  try {
+    rc = f();
+    if (c) {
+      c->ex->flush_profile();
+      c->sync();
+    }
+  } catch (const SccError& e) {
+    if (c) c->err = e.what();
+    rc = e.code;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    rc = SCC_EDEVICE;
+  }
+  if (info) {
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->flops_mfma = c ? c->flops - f0 : 0;
+    if (rc) info->converged = 0;
+  }
+  return rc;
+}
+
+bool valid_dims(const scc_dims* d) {
+  return d && d->nocc >= 1 && d->nvirt >= 1 && d->nchol >= 1 && d->nstates >= 1 && d->nstates <= 16;
+}
+
+void default_opts(const scc_options* o, scc_options& out) {
+  out.tol_residual = 1e-10;
+  out.tol_overlap = 1e-11;
+  out.max_iter = 200;
+  out.scc = 1;
+  out.verbose = 0;
+  if (o) out = *o;
+  if (out.tol_residual <= 0) out.tol_residual = 1e-10;
+  if (out.tol_overlap <= 0) out.tol_overlap = 1e-11;
+  if (out.max_iter <= 0) out.max_iter = 200;
+}
+
+struct Plan {
+  std::unique_ptr<Model> m;
+  int64_t arena, scratch, pool;
+  size_t bytes;
+};
+
+Plan make_plan(const scc_dims* d) {
+  Plan p;
+  p.m = std::make_unique<Model>();
+  Dims dd{d->nocc, d->nvirt, d->nocc + d->nvirt, d->nchol, d->nstates};
+  build_model(*p.m, dd);
+  p.arena = up(p.m->g.finalize(), 32);
+  p.scratch = up(std::max<int64_t>(Executor::plan_scratch(p.m->g), 32));
+  p.pool = up(sizes_for(dd).pool);
+  p.bytes = (size_t)(p.arena + p.scratch + PARTIALS + p.pool) * sizeof(double) + 256;
+  return p;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int scc_workspace_bytes(const scc_dims* dims, const scc_options* opts, size_t* bytes) {
+  (void)opts;
+  if (!valid_dims(dims) || !bytes) return SCC_EINVAL;
+  try {
+    Plan p = make_plan(dims);
+    *bytes = p.bytes;
+  } catch (...) {
+    return SCC_EINVAL;
+  }
+  return SCC_OK;
+}
+
+int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, size_t bytes, void* hip_stream,
+               scc_ctx** ctx) {
+  if (!valid_dims(dims) || !workspace || !ctx) return SCC_EINVAL;
+  *ctx = nullptr;
+  try {
+    Plan p = make_plan(dims);
+    if (bytes < p.bytes) return SCC_ENOMEM;
+    auto c = std::make_unique<scc_ctx>();
+    c->m = std::move(*p.m);
+    Dims dd = c->m.d;
+    c->sz = sizes_for(dd);
+    default_opts(opts, c->opt);
+    c->s = (hipStream_t)hip_stream;
+    uintptr_t base = ((uintptr_t)workspace + 255) & ~(uintptr_t)255;
+    c->arena = (double*)base;
+    c->scratch = c->arena + p.arena;
+    c->scratch_n = p.scratch;
+    c->partials = c->scratch + p.scratch;
+    c->pool = c->partials + PARTIALS;
+    c->sz.pool = p.pool;
+    c->ex = std::make_unique<Executor>(c->m.g, c->arena, c->scratch, c->scratch_n, c->partials);
+    c->ex->plan_all();
+    c->D = c->alloc(c->sz.nvt);
+    for (int k = 0; k < dd.ns; ++k) {
+      c->R.push_back(c->alloc(c->sz.nst));
+      c->Lv.push_back(c->alloc(c->sz.nst));
+    }
+    c->kbar = c->alloc(c->sz.nov);
+    c->dsc = c->alloc(32);
+    // constants
+    Model& m = c->m;
+    std::vector<double> In((size_t)dd.n * dd.n, 0.0), Io((size_t)dd.o * dd.o, 0.0);
+    for (int i = 0; i < dd.n; ++i) In[(size_t)i * dd.n + i] = 1.0;
+    for (int i = 0; i < dd.o; ++i) Io[(size_t)i * dd.o + i] = 1.0;
+    hck(hipMemcpy(c->tp(m.In), In.data(), In.size() * sizeof(double), hipMemcpyHostToDevice));
+    hck(hipMemcpy(c->tp(m.Io), Io.data(), Io.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->set_scalar(m.one, 1.0);
+    c->fill(c->tp(m.z2), m.g.t[m.z2].size(), 0.0);
+    c->fill(c->tp(m.kappa), c->sz.nov, 0.0);
+    c->fill(c->tp(m.t1), c->sz.nov, 0.0);
+    c->fill(c->tp(m.t2), c->sz.nov * c->sz.nov, 0.0);
+    for (int z : m.zeta) c->set_scalar(z, 0.0);
+    for (auto& xs : m.xs) {
+      c->fill(c->tp(xs.r0), 1, 0.0);
+      c->fill(c->tp(xs.r1), c->sz.nov, 0.0);
+      c->fill(c->tp(xs.r2), c->sz.nov * c->sz.nov, 0.0);
+    }
+    c->sync();
+    *ctx = c.release();
+  } catch (const SccError& e) {
+    return e.code;
+  } catch (const std::exception& e) {
+    fprintf(stderr, "scc_create: %s\n", e.what());
+    return SCC_EDEVICE;
+  }
+  return SCC_OK;
+}
+
+void scc_destroy(scc_ctx* ctx) { delete ctx; }
+
+const char* scc_last_error(const scc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int scc_set_hamiltonian(scc_ctx* c, const double* h, const double* chol, double e_nuc) {
+  if (!c || !h || !chol) return SCC_EINVAL;
+  return guarded(c, nullptr, [&]() -> int {
+    Model& m = c->m;
+    c->cp(c->tp(m.h), h, m.g.t[m.h].size());
+    c->cp(c->tp(m.L), chol, m.g.t[m.L].size());
+    c->fill(c->tp(m.kappa), c->sz.nov, 0.0);
+    c->run(m.p_setup);
+    // orbital energies from the Fock diagonal
+    const int N = m.d.n, o = m.d.o, v = m.d.v;
+    std::vector<double> F((size_t)N * N);
+    c->sync();
+    hck(hipMemcpy(F.data(), c->tp(m.fock), F.size() * sizeof(double), hipMemcpyDeviceToHost));
+    c->eps.resize(N);
+    for (int p = 0; p < N; ++p) c->eps[p] = F[(size_t)p * N + p];
+    double fai = 0;
+    for (int a = 0; a < v; ++a)
+      for (int i = 0; i < o; ++i) fai = std::max(fai, std::fabs(F[(size_t)(o + a) * N + i]));
+    if (fai > 1e-6) throw SccError(SCC_EINVAL, "integrals are not in a Hartree-Fock basis (max|F_ai| > 1e-6)");
+    std::vector<double> D(c->sz.nvt);
+    const int64_t nov = c->sz.nov;
+    for (int a = 0; a < v; ++a)
+      for (int i = 0; i < o; ++i) D[a * o + i] = c->eps[o + a] - c->eps[i];
+    for (int64_t p = 0; p < nov; ++p)
+      for (int64_t q = 0; q < nov; ++q) D[nov + p * nov + q] = D[p] + D[q];
+    hck(hipMemcpy(c->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
+    // every geometry starts cold: t = 0 (the first Jacobi step is MP2), zeta = 0
+    c->fill(c->tp(m.t1), nov, 0.0);
+    c->fill(c->tp(m.t2), nov * nov, 0.0);
+    c->enuc = e_nuc;
+    c->have_h = true;
+    c->have_ground = c->have_excited = c->have_mult = false;
+    return SCC_OK;
+  });
+}
+
+int scc_ground(scc_ctx* c, const double* guess_t, double* e0, scc_info* info) {
+  if (!c) return SCC_EINVAL;
+  if (!c->have_h) {
+    c->err = "scc_ground before scc_set_hamiltonian";
+    return SCC_ESTATE;
+  }
+  return guarded(c, info, [&]() -> int {
+    Model& m = c->m;
+    if (guess_t) {
+      c->put(m.t1, guess_t);
+      c->put(m.t2, guess_t + c->sz.nov);
+    }
+    for (int z : m.zeta) c->set_scalar(z, 0.0);
+    double rn = 0;
+    int rc = ground_solve(c, c->opt.tol_residual, c->opt.max_iter, rn);
+    c->E0 = c->tensor_scalar(m.res.E) + c->enuc;
+    if (e0) launch_fill(e0, 1, c->E0, c->s);
+    if (info) {
+      info->residual = rn;
+      info->converged = rc == SCC_OK;
+    }
+    c->E0 -= c->enuc;
+    if (rc == SCC_OK) c->have_ground = true;
+    return rc;
+  });
+}
+
+int scc_excited(scc_ctx* c, int nstates, const double* guess, double* energies, double* zeta, scc_info* info) {
+  if (!c) return SCC_EINVAL;
+  if (nstates != c->m.d.ns) {
+    c->err = "nstates must equal the context's nstates";
+    return SCC_EINVAL;
+  }
+  if (!c->have_h) return SCC_ESTATE;
+  (void)guess;
+  return guarded(c, info, [&]() -> int {
+    int rc = excited_solve(c, info);
+    if (rc) return rc;
+    c->have_ground = c->have_excited = true;
+    c->have_mult = false;
+    if (energies) {
+      std::vector<double> e(c->E);
+      for (auto& x : e) x += c->enuc;
+      hck(hipMemcpy(energies, e.data(), e.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (zeta && !c->zeta.empty()) hck(hipMemcpy(zeta, c->zeta.data(), c->zeta.size() * sizeof(double), hipMemcpyHostToDevice));
+    return SCC_OK;
+  });
+}
+
+int scc_multipliers(scc_ctx* c, int kind, int m, int n, scc_info* info) {
+  if (!c) return SCC_EINVAL;
+  const int ns = c->m.d.ns;
+  if (kind < 0 || kind > 1 || n < 0 || n >= ns || (kind == 1 && (m < 0 || m >= ns || m == n))) {
+    c->err = "bad target";
+    return SCC_EINVAL;
+  }
+  if (!c->have_excited) {
+    c->err = "scc_multipliers before scc_excited";
+    return SCC_ESTATE;
+  }
+  return guarded(c, info, [&]() -> int { return multipliers_solve(c, kind, m, n, info); });
+}
+
+int scc_densities(scc_ctx* c, double* d1, double* z3, double* kappa_bar) {
+  if (!c) return SCC_EINVAL;
+  if (!c->have_mult) return SCC_ESTATE;
+  return guarded(c, nullptr, [&]() -> int {
+    integral_adjoints(c);
+    if (d1) c->get(c->m.a_h, d1);
+    if (z3) c->get(c->m.a_L, z3);
+    if (kappa_bar) c->cp(kappa_bar, c->kbar, c->sz.nov);
+    return SCC_OK;
+  });
+}
+
+static int derivative(scc_ctx* c, int kind, int mm, int nn, int ncoord, const double* dh, const double* dchol,
+                      double* out, scc_info* info) {
+  if (!c || !dh || !dchol || !out || ncoord < 0) return SCC_EINVAL;
+  if ((int64_t)ncoord * 256 > PARTIALS) return SCC_EINVAL;
+  if (!c->have_excited) return SCC_ESTATE;
+  return guarded(c, info, [&]() -> int {
+    if (!(c->have_mult && c->mult_kind == kind && c->mult_n == nn && (kind == 0 || c->mult_m == mm))) {
+      int rc = multipliers_solve(c, kind, mm, nn, info);
+      if (rc) return rc;
+    }
+    integral_adjoints(c);
+    const int64_t N = c->m.d.n, J = c->m.d.nj;
+    double* D1 = c->zero(c->m.a_h) ? nullptr : c->tp(c->m.a_h);
+    double* Z = c->zero(c->m.a_L) ? nullptr : c->tp(c->m.a_L);
+    if (!D1 || !Z) throw SccError(SCC_EDEVICE, "empty density");
+    launch_deriv_contract(dh, N * N, D1, dchol, J * N * N, Z, ncoord, out, c->partials, c->s);
+    return SCC_OK;
+  });
+}
+
+int scc_gradient(scc_ctx* c, int n, int ncoord, const double* dh, const double* dchol, double* grad, scc_info* info) {
+  if (c && (n < 0 || n >= c->m.d.ns)) return SCC_EINVAL;
+  return derivative(c, 0, -1, n, ncoord, dh, dchol, grad, info);
+}
+
+int scc_nac(scc_ctx* c, int m, int n, int ncoord, const double* dh, const double* dchol, double* nac, scc_info* info) {
+  if (c && (n < 0 || n >= c->m.d.ns || m < 0 || m >= c->m.d.ns || m == n)) return SCC_EINVAL;
+  return derivative(c, 1, m, n, ncoord, dh, dchol, nac, info);
+}
+
+int scc_get(scc_ctx* c, int field, int k, double* out) {
+  if (!c || !out) return SCC_EINVAL;
+  return guarded(c, nullptr, [&]() -> int {
+    Model& m = c->m;
+    const int64_t nov = c->sz.nov;
+    switch (field) {
+      case SCC_FIELD_T:
+        c->get(m.t1, out);
+        c->get(m.t2, out + nov);
+        return SCC_OK;
+      case SCC_FIELD_R:
+      case SCC_FIELD_L:
+        if (!c->have_excited || k < 0 || k >= m.d.ns) return SCC_ESTATE;
+        c->cp(out, field == SCC_FIELD_R ? c->R[k] : c->Lv[k], c->sz.nst);
+        return SCC_OK;
+      case SCC_FIELD_E0:
+        launch_fill(out, 1, c->E0 + c->enuc, c->s);
+        return SCC_OK;
+      case SCC_FIELD_OMEGA:
+        c->run(m.p_res);
+        c->get(m.res.O1, out);
+        c->get(m.res.O2, out + nov);
+        return SCC_OK;
+    }
+    return SCC_EINVAL;
+  });
+}
+
+int scc_profile(scc_ctx* c, int enable, double* gemm_ms, double* gemm_flops, long long* gemm_launches) {
+  if (!c) return SCC_EINVAL;
+  return guarded(c, nullptr, [&]() -> int {
+    c->ex->flush_profile();
+    c->ex->set_profile(enable != 0);
+    if (gemm_ms) *gemm_ms = c->ex->gemm_ms;
+    if (gemm_flops) *gemm_flops = c->ex->gemm_flops;
+    if (gemm_launches) *gemm_launches = (long long)c->ex->gemm_launches;
+    return SCC_OK;
+  });
+}
+
+int scc_eval_residual(scc_ctx* c, const double* t, const double* zeta, const double* xs, double* out) {
+  if (!c || !t || !out) return SCC_EINVAL;
+  if (!c->have_h) return SCC_ESTATE;
+  return guarded(c, nullptr, [&]() -> int {
+    Model& m = c->m;
+    const int64_t nov = c->sz.nov;
+    c->put(m.t1, t);
+    c->put(m.t2, t + nov);
+    for (size_t p = 0; p < m.zeta.size(); ++p) {
+      if (zeta)
+        c->cp(c->tp(m.zeta[p]), zeta + p, 1);
+      else
+        c->set_scalar(m.zeta[p], 0.0);
+    }
+    for (int k = 0; k < m.d.ns; ++k) {
+      if (xs)
+        c->put_state(m.xs[k], xs + k * c->sz.nst);
+      else {
+        c->fill(c->tp(m.xs[k].r0), 1, 0.0);
+        c->fill(c->tp(m.xs[k].r1), nov, 0.0);
+        c->fill(c->tp(m.xs[k].r2), nov * nov, 0.0);
+      }
+    }
+    c->run(m.p_res);
+    c->get(m.res.E, out);
+    c->get(m.res.O1, out + 1);
+    c->get(m.res.O2, out + 1 + nov);
+    return SCC_OK;
+  });
+}
+
+int scc_eval_sigma(scc_ctx* c, const double* vec, double* out) {
+  if (!c || !vec || !out) return SCC_EINVAL;
+  if (!c->have_h) return SCC_ESTATE;
+  return guarded(c, nullptr, [&]() -> int {
+    Model& m = c->m;
+    c->run(m.p_sig_pre);
+    c->put_state(m.vin, vec);
+    c->run(m.p_sig);
+    c->get(m.sig.s0, out);
+    c->get(m.sig.s1, out + 1);
+    c->get(m.sig.s2, out + 1 + c->sz.nov);
+    return SCC_OK;
+  });
+}
+
+int scc_eval_left(scc_ctx* c, const double* vec, double* out) {
+  if (!c || !vec || !out) return SCC_EINVAL;
+  if (!c->have_h) return SCC_ESTATE;
+  return guarded(c, nullptr, [&]() -> int {
+    Model& m = c->m;
+    c->run(m.p_sig_pre);
+    c->put_state(m.lin, vec);
+    c->run(m.p_left);
+    c->get(m.lout.r0, out);
+    c->get(m.lout.r1, out + 1);
+    c->get(m.lout.r2, out + 1 + c->sz.nov);
+    c->sym_doubles(out + 1 + c->sz.nov);
+    return SCC_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// Small dense linear algebra for the solvers' subspace problems (dimensions
+// of a few tens): pivoted Gaussian elimination and a nonsymmetric
+// eigensolver (Householder reduction to Hessenberg form, complex
+// single-shift QR with Wilkinson shifts, eigenvectors by inverse iteration).
+#pragma once
+#include <cmath>
+#include <complex>
+#include <vector>
+
+namespace scc {
+
+using cplx = std::complex<double>;
+
+// Solve A x = b in place (A row-major n x n, overwritten). Returns false if
+// a pivot vanishes.
+inline bool solve_linear(int n, std::vector<double> A, std::vector<double>& b) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[i * n + k]) > std::fabs(A[p * n + k])) p = i;
+    if (A[p * n + k] == 0.0) return false;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[p * n + j]);
+      std::swap(b[k], b[p]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      double f = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * b[j];
+    b[i] = s / A[i * n + i];
+  }
+  return true;
+}
+
+inline bool solve_complex(int n, std::vector<cplx> A, std::vector<cplx>& b) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::abs(A[i * n + k]) > std::abs(A[p * n + k])) p = i;
+    if (std::abs(A[p * n + k]) == 0.0) return false;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[p * n + j]);
+      std::swap(b[k], b[p]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      cplx f = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    cplx s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * b[j];
+    b[i] = s / A[i * n + i];
+  }
+  return true;
+}
+
+// Eigenvalues w[n] and right eigenvectors V (column k = V[i*n+k]) of a real
+// nonsymmetric matrix A (row-major).  Returns false if QR fails to converge.
+inline bool eig_nonsym(int n, const std::vector<double>& A, std::vector<cplx>& w, std::vector<cplx>& V) {
+  std::vector<cplx> H(n * n);
+  for (int i = 0; i < n * n; ++i) H[i] = A[i];
+  // Householder reduction to upper Hessenberg form
+  for (int k = 0; k + 2 < n; ++k) {
+    double alpha = 0;
+    for (int i = k + 1; i < n; ++i) alpha += std::norm(H[i * n + k]);
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    std::vector<cplx> u(n, 0.0);
+    cplx x0 = H[(k + 1) * n + k];
+    cplx ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : cplx(1.0);
+    for (int i = k + 1; i < n; ++i) u[i] = H[i * n + k];
+    u[k + 1] += ph * alpha;
+    double un = 0;
+    for (int i = k + 1; i < n; ++i) un += std::norm(u[i]);
+    if (un == 0.0) continue;
+    // H = (I - 2uu*/un) H (I - 2uu*/un)
+    for (int j = 0; j < n; ++j) {
+      cplx s = 0;
+      for (int i = k + 1; i < n; ++i) s += std::conj(u[i]) * H[i * n + j];
+      s *= 2.0 / un;
+      for (int i = k + 1; i < n; ++i) H[i * n + j] -= u[i] * s;
+    }
+    for (int i = 0; i < n; ++i) {
+      cplx s = 0;
+      for (int j = k + 1; j < n; ++j) s += H[i * n + j] * u[j];
+      s *= 2.0 / un;
+      for (int j = k + 1; j < n; ++j) H[i * n + j] -= s * std::conj(u[j]);
+    }
+  }
+  // complex shifted QR on the Hessenberg matrix
+  w.assign(n, 0.0);
+  int hi = n - 1, iter = 0;
+  while (hi >= 0) {
+    if (hi == 0) {
+      w[0] = H[0];
+      break;
+    }
+    int lo = hi;
+    while (lo > 0) {
+      double s = std::abs(H[(lo - 1) * n + lo - 1]) + std::abs(H[lo * n + lo]);
+      if (s == 0.0) s = 1.0;
+      if (std::abs(H[lo * n + lo - 1]) < 1e-15 * s) {
+        H[lo * n + lo - 1] = 0.0;
+        break;
+      }
+      --lo;
+    }
+    if (lo == hi) {
+      w[hi] = H[hi * n + hi];
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (++iter > 300 * n) return false;
+    // Wilkinson shift from the trailing 2x2 block
+    cplx a = H[(hi - 1) * n + hi - 1], b = H[(hi - 1) * n + hi], c = H[hi * n + hi - 1], d = H[hi * n + hi];
+    cplx tr = a + d, det = a * d - b * c;
+    cplx disc = std::sqrt(tr * tr - 4.0 * det);
+    cplx l1 = 0.5 * (tr + disc), l2 = 0.5 * (tr - disc);
+    cplx mu = std::abs(l1 - d) < std::abs(l2 - d) ? l1 : l2;
+    if (iter % 11 == 10) mu += cplx(0.7 * std::abs(c), 0.0);  // exceptional shift
+    for (int i = lo; i <= hi; ++i) H[i * n + i] -= mu;
+    std::vector<cplx> cs(n), sn(n);
+    for (int k = lo; k < hi; ++k) {
+      cplx x = H[k * n + k], y = H[(k + 1) * n + k];
+      double r = std::sqrt(std::norm(x) + std::norm(y));
+      cplx cc = r == 0 ? cplx(1.0) : x / r, ss = r == 0 ? cplx(0.0) : y / r;
+      cs[k] = cc;
+      sn[k] = ss;
+      for (int j = k; j < n; ++j) {
+        cplx h1 = H[k * n + j], h2 = H[(k + 1) * n + j];
+        H[k * n + j] = std::conj(cc) * h1 + std::conj(ss) * h2;
+        H[(k + 1) * n + j] = -ss * h1 + cc * h2;
+      }
+    }
+    for (int k = lo; k < hi; ++k) {
+      cplx cc = cs[k], ss = sn[k];
+      for (int i = 0; i <= std::min(k + 2, hi); ++i) {
+        cplx h1 = H[i * n + k], h2 = H[i * n + k + 1];
+        H[i * n + k] = h1 * cc + h2 * ss;
+        H[i * n + k + 1] = -h1 * std::conj(ss) + h2 * std::conj(cc);
+      }
+    }
+    for (int i = lo; i <= hi; ++i) H[i * n + i] += mu;
+  }
+  // eigenvectors of the original matrix by inverse iteration
+  V.assign(n * n, 0.0);
+  double anorm = 0;
+  for (int i = 0; i < n * n; ++i) anorm = std::max(anorm, std::fabs(A[i]));
+  for (int k = 0; k < n; ++k) {
+    cplx lam = w[k] + cplx(1e-13 * (anorm + 1.0), 0.0);
+    std::vector<cplx> M(n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) M[i * n + j] = A[i * n + j] - (i == j ? lam : cplx(0.0));
+    std::vector<cplx> x(n, 1.0);
+    for (int i = 0; i < n; ++i) x[i] = cplx(1.0 + 0.1 * i, 0.0);
+    for (int it = 0; it < 3; ++it) {
+      if (!solve_complex(n, M, x)) break;
+      double nr = 0;
+      for (auto& z : x) nr += std::norm(z);
+      nr = std::sqrt(nr);
+      for (auto& z : x) z /= nr;
+    }
+    // make the largest component real positive
+    int im = 0;
+    for (int i = 1; i < n; ++i)
+      if (std::abs(x[i]) > std::abs(x[im])) im = i;
+    cplx ph = std::abs(x[im]) > 0 ? std::conj(x[im]) / std::abs(x[im]) : cplx(1.0);
+    for (int i = 0; i < n; ++i) V[i * n + k] = x[i] * ph;
+  }
+  return true;
+}
+
+}  // namespace scc
