@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -55,12 +56,12 @@ Sizes sizes_for(const Dims& d) {
   s.nvt = s.nov + s.nov * s.nov;
   s.nst = 1 + s.nvt;
   s.nlag = s.nvt + d.ns * (s.nst + 1) + d.npairs();
-  s.maxsub = std::max(20, 8 * d.ns + 8);
+  s.maxsub = std::max(40, 12 * d.ns + 24);
   int64_t p = 0;
   p += up(s.nvt);                       // D
   p += 2 * d.ns * up(s.nst);            // R, L
   p += 2 * NDIIS * up(s.nvt) + 3 * up(s.nvt);
-  p += 2 * s.maxsub * up(s.nvt) + 4 * (d.ns + 2) * up(s.nvt) + 2 * up(s.nvt);
+  p += 2 * s.maxsub * up(s.nvt) + 6 * (d.ns + 2) * up(s.nvt) + 2 * up(s.nvt);
   p += (2 * GMRES_M + 4) * up(s.nlag);
   p += (2 * GMRES_M + 4) * up(s.nov) + 2 * up(s.nov);
   p += 64;
@@ -259,26 +260,30 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
              std::vector<double>& evals, std::vector<double*>& out, int& iters) {
   const int64_t nvt = c->sz.nvt, nov = c->sz.nov;
   const int maxsub = c->sz.maxsub;
+  // nwork Ritz pairs are refined; the nbuf above the requested ones only
+  // keep a nearby root from slowing the convergence of the last requested one
+  const int nbuf = 2;
+  const int nwork = nroots + nbuf;
+  const int nkeep = std::min(maxsub / 2, 2 * nwork);
+  const double pfloor = 0.05;
   int64_t mark = c->pool_used;
   std::vector<double*> V(maxsub), W(maxsub);
   for (int i = 0; i < maxsub; ++i) {
     V[i] = c->alloc(nvt);
     W[i] = c->alloc(nvt);
   }
-  const int nx = nroots + 2;
-  std::vector<double*> Xr(nx), Xw(nx), Rs(nx);
-  for (int i = 0; i < nx; ++i) {
+  std::vector<double*> Xr(nkeep), Xw(nkeep), Rs(nwork);
+  for (int i = 0; i < nkeep; ++i) {
     Xr[i] = c->alloc(nvt);
     Xw[i] = c->alloc(nvt);
-    Rs[i] = c->alloc(nvt);
   }
+  for (int i = 0; i < nwork; ++i) Rs[i] = c->alloc(nvt);
   double* q = c->alloc(nvt);
   int nv = 0;
   auto add_vector = [&](double* src) -> bool {
     double n0 = std::sqrt(c->dot(src, src, nvt));
     if (!(n0 > 0)) return false;
     c->axpby(0.0, src, 1.0 / n0, src, nvt);
-    // two passes of modified Gram-Schmidt against V
     for (int pass = 0; pass < 2; ++pass)
       for (int j = 0; j < nv; ++j) {
         double h = c->dot(V[j], src, nvt);
@@ -291,25 +296,24 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     ++nv;
     return true;
   };
-  if (!guess.empty()) {
-    for (auto* gv : guess) {
-      c->cp(q, gv + 1, nvt);
-      add_vector(q);
-    }
+  for (auto* gv : guess) {
+    c->cp(q, gv + 1, nvt);
+    add_vector(q);
   }
-  if (nv < nx) {
+  if (nv < nwork) {
     // unit vectors on the smallest singles denominators
     std::vector<double> dh(nov);
     hck(hipMemcpy(dh.data(), c->D, nov * sizeof(double), hipMemcpyDeviceToHost));
     std::vector<int> idx(nov);
     for (int64_t i = 0; i < nov; ++i) idx[i] = (int)i;
     std::sort(idx.begin(), idx.end(), [&](int a, int b) { return dh[a] < dh[b]; });
-    for (int64_t k = 0; k < nov && nv < nx; ++k) {
+    for (int64_t k = 0; k < nov && nv < std::max(nwork, nroots + 2); ++k) {
       c->fill(q, nvt, 0.0);
       launch_fill(q + idx[k], 1, 1.0, c->s);
       add_vector(q);
     }
   }
+  const int nw_ = std::min<int>(nwork, nv);
   std::vector<double> G(maxsub * maxsub, 0.0);
   int nw = 0, ng = 0;
   iters = 0;
@@ -328,10 +332,12 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     std::vector<int> ord(nv);
     for (int i = 0; i < nv; ++i) ord[i] = i;
     std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
+    const int nr_now = std::min(nw_, nv);
+    const int nx = std::min(nkeep, nv);
     double maxres = 0;
-    std::vector<double> th(nroots);
-    std::vector<char> conv(nroots, 0);
-    for (int k = 0; k < nroots; ++k) {
+    std::vector<double> th(nx);
+    std::vector<char> conv(nx, 0);
+    for (int k = 0; k < nx; ++k) {
       int col = ord[k];
       th[k] = w[col].real();
       // a complex-conjugate Ritz pair contributes Re(y) and Im(y)
@@ -350,34 +356,42 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
         c->axpby(y[j] / yn, V[j], 1.0, Xr[k], nvt);
         c->axpby(y[j] / yn, W[j], 1.0, Xw[k], nvt);
       }
-      c->cp(Rs[k], Xw[k], nvt);
-      c->axpby(-th[k], Xr[k], 1.0, Rs[k], nvt);
-      double rn = std::sqrt(c->dot(Rs[k], Rs[k], nvt));
-      maxres = std::max(maxres, rn);
-      conv[k] = rn < tol;
-      if (cplx_pair) conv[k] = 0;
+      if (k < nr_now) {
+        c->cp(Rs[k], Xw[k], nvt);
+        c->axpby(-th[k], Xr[k], 1.0, Rs[k], nvt);
+        double rn = std::sqrt(c->dot(Rs[k], Rs[k], nvt));
+        if (k < nroots) maxres = std::max(maxres, rn);
+        conv[k] = rn < tol && !cplx_pair;
+      }
     }
-    c->log("  %s davidson it %3d  nv %2d  max|r| %.3e  theta0 %.10f\n", left ? "left " : "right", it, nv, maxres,
-           th[0]);
-    if (maxres < tol) {
-      evals = th;
+    if (c->opt.verbose) {
+      c->log("  %s davidson it %3d  nv %2d  max|r| %.3e", left ? "left " : "right", it, nv, maxres);
+      for (int k = 0; k < nroots; ++k) c->log("  w%d %.8f%s", k, th[k] - c->E0, conv[k] ? "*" : "");
+      c->log("\n");
+    }
+    bool done = true;
+    for (int k = 0; k < nroots; ++k) done = done && conv[k];
+    if (done) {
+      evals.assign(th.begin(), th.begin() + nroots);
       for (int k = 0; k < nroots; ++k) c->cp(out[k], Xr[k], nvt);
       c->pool_used = mark;
       return SCC_OK;
     }
     int nnew = 0;
-    for (int k = 0; k < nroots; ++k)
+    for (int k = 0; k < nr_now; ++k)
       if (!conv[k]) ++nnew;
     if (nv + nnew > maxsub) {
-      // collapse onto the current Ritz vectors (orthonormalised)
+      // thick restart on the lowest nkeep Ritz vectors (orthonormalised)
       nv = 0;
-      for (int k = 0; k < nroots; ++k) {
-        for (int j = 0; j < nv; ++j) {
-          double h = c->dot(V[j], Xr[k], nvt);
-          c->axpby(-h, V[j], 1.0, Xr[k], nvt);
-          c->axpby(-h, W[j], 1.0, Xw[k], nvt);
-        }
+      for (int k = 0; k < nx; ++k) {
+        for (int pass = 0; pass < 2; ++pass)
+          for (int j = 0; j < nv; ++j) {
+            double h = c->dot(V[j], Xr[k], nvt);
+            c->axpby(-h, V[j], 1.0, Xr[k], nvt);
+            c->axpby(-h, W[j], 1.0, Xw[k], nvt);
+          }
         double nr = std::sqrt(c->dot(Xr[k], Xr[k], nvt));
+        if (nr < 1e-8) continue;
         c->cp(V[nv], Xr[k], nvt);
         c->axpby(0.0, Xr[k], 1.0 / nr, V[nv], nvt);
         c->cp(W[nv], Xw[k], nvt);
@@ -387,9 +401,10 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       nw = nv;
       ng = 0;
     }
-    for (int k = 0; k < nroots; ++k) {
+    for (int k = 0; k < nr_now; ++k) {
       if (conv[k]) continue;
-      launch_precond(Rs[k], c->D, th[k], 1e-3, q, nvt, c->s);
+      // (D - omega)^-1 with omega = theta - E0 (Hbar carries E0 on its diagonal)
+      launch_precond(Rs[k], c->D, th[k] - c->E0, pfloor, q, nvt, c->s);
       c->sym_doubles(q + nov);
       if (nv < maxsub) add_vector(q);
     }

@@ -1,0 +1,67 @@
+"""Device programs at the full o10v90 workload (o=10, v=90, N_J=300, three
+states in X3) against the FP64 oracle evaluated on the host CPU, every
+element of the residual and of the right transformation."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cc
+from synth_inputs import make_system, random_amplitudes
+
+pytestmark = pytest.mark.gpu
+
+T = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float64)
+
+
+def _flat(r):
+    return np.concatenate([[r[0]], np.asarray(r[1]).ravel(), np.asarray(r[2]).ravel()])
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2403_01007_amd import Context
+    S = make_system("o10v90")
+    print("[case o10v90 full-size parity]", flush=True)
+    h, L = S.at(np.zeros(S.ncoord))
+    ctx = Context(S.o, S.v, S.nj, S.nstates)
+    ctx.set_hamiltonian(h, L)
+    t1, t2 = random_amplitudes(S.o, S.v, seed=5, scale=0.005)
+    amps = random_amplitudes(S.o, S.v, seed=9, scale=0.02, nvec=S.nstates + 1)
+    states = [(0.1 * (k + 1), amps[k][0], amps[k][1]) for k in range(S.nstates)]
+    zeta = np.array([0.3, -0.2, 0.15])
+    vec = (0.2, amps[-1][0], amps[-1][1])
+    t0 = time.time()
+    g = torch.einsum("Jpq,Jrs->pqrs", T(L), T(L))
+    print(f"  oracle integrals {time.time() - t0:.1f}s", flush=True)
+    return S, ctx, h, g, t1, t2, states, zeta, vec
+
+
+def test_fullsize_residual(full):
+    S, ctx, h, g, t1, t2, states, zeta, vec = full
+    nov = S.o * S.v
+    t = np.concatenate([t1.ravel(), t2.ravel()])
+    out = ctx.eval_residual(t, zeta, np.stack([_flat(r) for r in states])).cpu().numpy()
+    t0 = time.time()
+    rs = [tuple(T(x) for x in r) for r in states]
+    E, s, d = cc.residual(T(h), g, T(t1), T(t2), S.o, T(zeta), rs)
+    print(f"  oracle residual {time.time() - t0:.1f}s", flush=True)
+    assert abs(out[0] - float(E)) < 1e-9
+    np.testing.assert_allclose(out[1:1 + nov], s.numpy().ravel(), rtol=0, atol=1e-11)
+    np.testing.assert_allclose(out[1 + nov:], d.numpy().ravel(), rtol=0, atol=1e-11)
+
+
+def test_fullsize_sigma(full):
+    S, ctx, h, g, t1, t2, states, zeta, vec = full
+    nov = S.o * S.v
+    t = np.concatenate([t1.ravel(), t2.ravel()])
+    ctx.eval_residual(t, zeta, np.stack([_flat(r) for r in states]))
+    out = ctx.eval_sigma(_flat(vec)).cpu().numpy()
+    t0 = time.time()
+    rs = [tuple(T(x) for x in r) for r in states]
+    s0, s1, s2 = cc.sigma(T(h), g, T(t1), T(t2), S.o, T(vec[0]), T(vec[1]), T(vec[2]), T(zeta), rs)
+    print(f"  oracle sigma {time.time() - t0:.1f}s", flush=True)
+    assert abs(out[0] - float(s0)) < 1e-9
+    np.testing.assert_allclose(out[1:1 + nov], s1.numpy().ravel(), rtol=0, atol=1e-10)
+    np.testing.assert_allclose(out[1 + nov:], s2.numpy().ravel(), rtol=0, atol=1e-10)
