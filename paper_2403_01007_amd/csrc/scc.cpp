@@ -46,7 +46,7 @@ int64_t up(int64_t x, int64_t a = 32) { return (x + a - 1) / a * a; }
 
 struct Sizes {
   int64_t nov, nvt, nst, nlag;
-  int maxsub;
+  int maxsub, cap_lag, cap_k;
   int64_t pool;
 };
 
@@ -62,12 +62,25 @@ Sizes sizes_for(const Dims& d) {
   p += 2 * d.ns * up(s.nst);            // R, L
   p += 2 * NDIIS * up(s.nvt) + 3 * up(s.nvt);
   p += 2 * s.maxsub * up(s.nvt) + 6 * (d.ns + 2) * up(s.nvt) + 2 * up(s.nvt);
-  p += (2 * GMRES_M + 4) * up(s.nlag);
-  p += (2 * GMRES_M + 4) * up(s.nov) + 2 * up(s.nov);
+  // recycled GCR spaces: Lagrangian (budget 32 GB) and orbital response
+  s.cap_lag = (int)std::max<int64_t>(20, std::min<int64_t>(400, (int64_t)(32e9 / (16.0 * up(s.nlag)))));
+  s.cap_k = 300;
+  p += 2 * (int64_t)s.cap_lag * up(s.nlag) + up(s.cap_lag) + 4 * up(s.nlag);
+  p += 2 * (int64_t)s.cap_k * up(s.nov) + up(s.cap_k) + 4 * up(s.nov);
   p += 64;
   s.pool = p;
   return s;
 }
+
+// GCR recycling space (see gcr below)
+struct Recycler {
+  int64_t n = 0;
+  int cap = 0, k = 0;
+  double* U = nullptr;     // [cap][n] search directions
+  double* C = nullptr;     // [cap][n] their images, orthonormal
+  double* coef = nullptr;  // [cap] device scratch
+  void reset() { k = 0; }
+};
 
 }  // namespace
 
@@ -89,6 +102,7 @@ struct scc_ctx {
   std::vector<double*> R, Lv; // states [r0 | r1 | r2]
   double* kbar = nullptr;
   double* dsc = nullptr;      // device scalars
+  Recycler rec_lag, rec_k;    // recycled Krylov spaces of the multiplier solves
   std::vector<double> eps;
   bool have_h = false, have_ground = false, have_excited = false, have_mult = false;
   double E0 = 0.0, enuc = 0.0;
@@ -184,7 +198,8 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
   }
   c->get(m.t1, x);
   c->get(m.t2, x + nov);
-  int nh = 0, head = 0, it = 0;
+  int nh = 0, head = 0, it = 0, since_best = 0;
+  double best = 1e300;
   std::vector<double> B(NDIIS * NDIIS, 0.0);
   for (it = 0; it < maxit; ++it) {
     c->put(m.t1, x);
@@ -192,9 +207,20 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
     c->run(m.p_res);
     c->get(m.res.O1, r);
     c->get(m.res.O2, r + nov);
+    c->sym_doubles(r + nov);
     rn = std::sqrt(c->dot(r, r, nvt));
     c->log("  ground it %3d  |Omega| %.3e\n", it, rn);
     if (rn < tol) break;
+    // restart the extrapolation when it stagnates
+    if (rn < best) {
+      best = rn;
+      since_best = 0;
+    } else if (++since_best >= 8) {
+      nh = 0;
+      head = 0;
+      since_best = 0;
+      best = rn;
+    }
     launch_precond(r, c->D, 0.0, 1e-8, e, nvt, c->s);
     int slot = head;
     head = (head + 1) % NDIIS;
@@ -222,6 +248,7 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
     }
     c->fill(x, nvt, 0.0);
     for (int i = 0; i < nh; ++i) c->axpby(b[i], X[i], 1.0, x, nvt);
+    c->sym_doubles(x + nov);
   }
   c->put(m.t1, x);
   c->put(m.t2, x + nov);
@@ -700,6 +727,155 @@ int gmres(scc_ctx* c, int64_t n, const LinOp& A, const LinOp& Minv, const double
 }
 
 // ---------------------------------------------------------------------------
+// GCR with recycling: pairs (u_i, c_i = A u_i), c_i orthonormal, kept across
+// right-hand sides of the same operator (all gradient / coupling targets share
+// the Lagrangian Jacobian).  Equivalent to unrestarted GMRES for one RHS.
+// ---------------------------------------------------------------------------
+// out[i] = C[i] . r for i < k (host copy returned)
+std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, const double* r) {
+  std::vector<double> h(k);
+  if (k == 0) return h;
+  double* dout = c->dsc + 16;
+  double* tmp = c->alloc(k);
+  launch_deriv_contract(Cb, n, r, Cb, 0, r, k, tmp, c->partials, c->s);
+  c->sync();
+  hck(hipMemcpy(h.data(), tmp, k * sizeof(double), hipMemcpyDeviceToHost));
+  c->pool_used -= up(k);
+  (void)dout;
+  return h;
+}
+
+// y += sum_i coef_i X[i] (X [k][n]) as one GEMV on the matrix cores
+void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* devcoef,
+                double* y) {
+  if (k == 0) return;
+  hck(hipMemcpyAsync(devcoef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice, c->s));
+  GemmArgs g{};
+  g.M = n;
+  g.N = 1;
+  g.K = k;
+  g.batch = 1;
+  g.alpha = 1.0;
+  g.beta = 1.0;
+  g.A = Xb;
+  g.sAm = 1;
+  g.sAk = n;
+  g.B = devcoef;
+  g.sBk = 1;
+  g.sBn = 0;
+  g.Cin = y;
+  g.C = y;
+  g.sCm = 1;
+  g.sCn = 0;
+  launch_gemm(g, c->s);
+}
+
+int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const double* b, double* x, double tol,
+        int maxit, int& iters, double& relres) {
+  const int64_t n = rc.n;
+  int64_t mark = c->pool_used;
+  double* r = c->alloc(n);
+  double* z = c->alloc(n);
+  double* w = c->alloc(n);
+  double bn = std::sqrt(c->dot(b, b, n));
+  c->fill(x, n, 0.0);
+  c->cp(r, b, n);
+  iters = 0;
+  relres = 1.0;
+  if (bn == 0) {
+    c->pool_used = mark;
+    relres = 0;
+    return SCC_OK;
+  }
+  rc.reset();
+  if (rc.k > 0) {
+    auto al = multi_dot(c, rc.C, rc.k, n, r);
+    multi_axpy(c, rc.U, rc.k, n, al, rc.coef, x);
+    for (auto& v : al) v = -v;
+    multi_axpy(c, rc.C, rc.k, n, al, rc.coef, r);
+  }
+  int checks = 0;
+  for (int it = 0; it < maxit; ++it) {
+    relres = std::sqrt(c->dot(r, r, n)) / bn;
+    if (it % 10 == 0) c->log("  gcr it %3d (stored %d)  rel. residual %.3e\n", it, rc.k, relres);
+    if (relres < tol) {
+      // confirm with the true residual b - A x before accepting
+      A(x, w);
+      c->cp(r, b, n);
+      c->axpby(-1.0, w, 1.0, r, n);
+      double tr = std::sqrt(c->dot(r, r, n)) / bn;
+      c->log("  gcr it %3d  true rel. residual %.3e\n", it, tr);
+      if (tr < 10 * tol || ++checks > 3) {
+        relres = tr;
+        c->pool_used = mark;
+        return tr < 10 * tol ? SCC_OK : SCC_ENOCONV;
+      }
+      // continue from the true residual (its direction re-seeds the space)
+      Minv(r, z);
+      A(z, w);
+      for (int pass = 0; pass < 2; ++pass) {
+        auto be = multi_dot(c, rc.C, rc.k, n, w);
+        for (auto& v : be) v = -v;
+        multi_axpy(c, rc.C, rc.k, n, be, rc.coef, w);
+        multi_axpy(c, rc.U, rc.k, n, be, rc.coef, z);
+      }
+      double wn = std::sqrt(c->dot(w, w, n));
+      if (!(wn > 0) || rc.k >= rc.cap) break;
+      double* un = rc.U + (int64_t)rc.k * n;
+      double* cn = rc.C + (int64_t)rc.k * n;
+      c->cp(un, z, n);
+      c->axpby(0.0, z, 1.0 / wn, un, n);
+      c->cp(cn, w, n);
+      c->axpby(0.0, w, 1.0 / wn, cn, n);
+      ++rc.k;
+      // project the true residual on the whole stored space
+      auto al = multi_dot(c, rc.C, rc.k, n, r);
+      multi_axpy(c, rc.U, rc.k, n, al, rc.coef, x);
+      for (auto& v : al) v = -v;
+      multi_axpy(c, rc.C, rc.k, n, al, rc.coef, r);
+      continue;
+    }
+    if (rc.k >= rc.cap) break;
+    // next direction from the last orthonormal image (the Krylov space of
+    // GMRES); starting from the residual alone stalls when A M^-1 r is
+    // orthogonal to r, which happens for the bordered multiplier system
+    ++iters;
+    if (it == 0 || rc.k == 0)
+      Minv(r, z);
+    else
+      Minv(rc.C + (int64_t)(rc.k - 1) * n, z);
+    A(z, w);
+    const double w0 = std::sqrt(c->dot(w, w, n));
+    // orthogonalise w against the stored c_i (twice), mirror on z
+    for (int pass = 0; pass < 2; ++pass) {
+      auto be = multi_dot(c, rc.C, rc.k, n, w);
+      std::vector<double> nb(be.size());
+      for (size_t i = 0; i < be.size(); ++i) nb[i] = -be[i];
+      multi_axpy(c, rc.C, rc.k, n, nb, rc.coef, w);
+      multi_axpy(c, rc.U, rc.k, n, nb, rc.coef, z);
+    }
+    double wn = std::sqrt(c->dot(w, w, n));
+    if (!(wn > 1e-12 * w0)) {
+      // the Krylov space is (numerically) invariant: confirm with the true residual
+      relres = 0.0;
+      continue;
+    }
+    double* un = rc.U + (int64_t)rc.k * n;
+    double* cn = rc.C + (int64_t)rc.k * n;
+    c->cp(un, z, n);
+    c->axpby(0.0, z, 1.0 / wn, un, n);
+    c->cp(cn, w, n);
+    c->axpby(0.0, w, 1.0 / wn, cn, n);
+    ++rc.k;
+    double al = c->dot(cn, r, n);
+    c->axpby(al, un, 1.0, x, n);
+    c->axpby(-al, cn, 1.0, r, n);
+  }
+  c->pool_used = mark;
+  return relres < tol ? SCC_OK : SCC_ENOCONV;
+}
+
+// ---------------------------------------------------------------------------
 // Lagrangian: parameters, multipliers, targets
 // ---------------------------------------------------------------------------
 struct Seg {
@@ -806,7 +982,8 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   };
   int iters = 0;
   double rel = 0;
-  int rc = gmres(c, n, apply, prec, b, x, c->opt.tol_residual, c->opt.max_iter, iters, rel);
+  int rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, std::max(c->opt.max_iter, c->rec_lag.cap),
+               iters, rel);
   if (rc) {
     c->pool_used = mark;
     return rc;
@@ -847,7 +1024,8 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   c->fill(c->kbar, nov, 0.0);
   int itk = 0;
   double relk = 0;
-  rc = gmres(c, nov, applyF, precF, rhs, c->kbar, c->opt.tol_residual, c->opt.max_iter, itk, relk);
+  rc = gcr(c, c->rec_k, applyF, precF, rhs, c->kbar, c->opt.tol_residual, std::max(c->opt.max_iter, c->rec_k.cap),
+           itk, relk);
   c->put(m.mF, c->kbar);
   c->pool_used = mark;
   if (rc) return rc;
@@ -979,6 +1157,16 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     }
     c->kbar = c->alloc(c->sz.nov);
     c->dsc = c->alloc(32);
+    c->rec_lag.n = c->sz.nlag;
+    c->rec_lag.cap = c->sz.cap_lag;
+    c->rec_lag.U = c->alloc((int64_t)c->sz.cap_lag * up(c->sz.nlag));
+    c->rec_lag.C = c->alloc((int64_t)c->sz.cap_lag * up(c->sz.nlag));
+    c->rec_lag.coef = c->alloc(c->sz.cap_lag);
+    c->rec_k.n = c->sz.nov;
+    c->rec_k.cap = c->sz.cap_k;
+    c->rec_k.U = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
+    c->rec_k.C = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
+    c->rec_k.coef = c->alloc(c->sz.cap_k);
     // constants
     Model& m = c->m;
     std::vector<double> In((size_t)dd.n * dd.n, 0.0), Io((size_t)dd.o * dd.o, 0.0);
@@ -1044,6 +1232,8 @@ int scc_set_hamiltonian(scc_ctx* c, const double* h, const double* chol, double 
     c->enuc = e_nuc;
     c->have_h = true;
     c->have_ground = c->have_excited = c->have_mult = false;
+    c->rec_lag.reset();
+    c->rec_k.reset();
     return SCC_OK;
   });
 }
@@ -1088,6 +1278,8 @@ int scc_excited(scc_ctx* c, int nstates, const double* guess, double* energies, 
     if (rc) return rc;
     c->have_ground = c->have_excited = true;
     c->have_mult = false;
+    c->rec_lag.reset();
+    c->rec_k.reset();
     if (energies) {
       std::vector<double> e(c->E);
       for (auto& x : e) x += c->enuc;
