@@ -48,18 +48,24 @@ def main():
     dL = torch.as_tensor(S.dL, device=dev)
     flops = [0.0]
 
+    def phase(name, info):
+        flops[0] += info.flops_mfma
+        if args.verbose:
+            print(f"[phase {name}: {info.seconds:.2f} s, {info.iterations} iterations, "
+                  f"{info.flops_mfma / 1e12:.2f} TFLOP]", file=sys.stderr, flush=True)
+
     def step():
         ctx.set_hamiltonian(h_d, L_d)
         E, zeta, info = ctx.excited()
-        flops[0] += info.flops_mfma
+        phase("excited", info)
         out = {"E": E, "zeta": zeta}
         for n in range(S.nstates):
             g, info = ctx.gradient(n, dh, dL)
-            flops[0] += info.flops_mfma
+            phase(f"gradient {n}", info)
             out[f"g{n}"] = g
         for (m, n) in S.nacs:
             d, info = ctx.nac(m, n, dh, dL)
-            flops[0] += info.flops_mfma
+            phase(f"coupling {m},{n}", info)
             out[f"d{m}{n}"] = d
         return out
 

@@ -152,7 +152,8 @@ int scc_get(scc_ctx* ctx, int field, int k, double* out);
  * every GEMM launch with HIP events on the context's stream (0 stops and
  * clears nothing).  On return (host pointers, any may be NULL): accumulated
  * kernel milliseconds, algorithmic flops (2 M N K per launch) and launches
- * since the context was created. */
+ * since the context was created.  With the verbose option, enable = 0 also
+ * prints the time per GEMM shape on stderr. */
 int scc_profile(scc_ctx* ctx, int enable, double* gemm_ms, double* gemm_flops, long long* gemm_launches);
 
 /* Test hooks on the device programs (inputs/outputs device pointers):

@@ -332,6 +332,48 @@ def scc_solve(h, g, o, eps, nstates, scc=True, tol=1e-12, maxiter=60,
 # ---------------------------------------------------------------------------
 # Lagrangian
 # ---------------------------------------------------------------------------
+def gmres(A, Minv, b, tol, maxiter, log=None):
+    """Right-preconditioned GMRES without restarts (Arnoldi with two passes of
+    modified Gram-Schmidt, Givens rotations for the least-squares problem)."""
+    n = b.size
+    bn = np.linalg.norm(b)
+    if bn == 0:
+        return np.zeros(n), 0
+    V = [b / bn]
+    Z = []
+    H = np.zeros((maxiter + 1, maxiter))
+    cs, sn = np.zeros(maxiter), np.zeros(maxiter)
+    g = np.zeros(maxiter + 1)
+    g[0] = bn
+    k = 0
+    for j in range(maxiter):
+        z = Minv(V[j])
+        w = A(z)
+        Z.append(z)
+        for _ in range(2):
+            for i in range(j + 1):
+                hij = V[i] @ w
+                H[i, j] += hij
+                w = w - hij * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V.append(w / H[j + 1, j] if H[j + 1, j] > 0 else w)
+        for i in range(j):
+            a, c_ = H[i, j], H[i + 1, j]
+            H[i, j], H[i + 1, j] = cs[i] * a + sn[i] * c_, -sn[i] * a + cs[i] * c_
+        r = np.hypot(H[j, j], H[j + 1, j])
+        cs[j], sn[j] = H[j, j] / r, H[j + 1, j] / r
+        H[j, j], H[j + 1, j] = r, 0.0
+        g[j + 1], g[j] = -sn[j] * g[j], cs[j] * g[j]
+        k = j + 1
+        if log is not None and j % 20 == 0:
+            log(f"    gmres {j} rel. residual {abs(g[j + 1]) / bn:.3e}")
+        if abs(g[j + 1]) / bn < tol:
+            break
+    y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
+    x = sum(yi * zi for yi, zi in zip(y, Z))
+    return x, k
+
+
 class Lagrangian:
     """Constraint functions e(lambda; kappa, h, g) of the gradient/coupling
     Lagrangians (eq. Lagrangian_gradient / Lagrangian_coupling)."""
@@ -420,7 +462,7 @@ class Lagrangian:
         return val
 
     # multipliers -------------------------------------------------------------
-    def solve_multipliers(self, kind, m, n, tol=1e-13, maxiter=3000):
+    def solve_multipliers(self, kind, m, n, tol=1e-12, maxiter=1500):
         s = self.sol
         lam = self.lam0().requires_grad_(True)
         kap = torch.zeros((s.v, s.o), dtype=f64, requires_grad=True)
@@ -437,17 +479,27 @@ class Lagrangian:
             (gl,) = torch.autograd.grad(e, lam, u, retain_graph=True)
             return gl.numpy()
 
-        # preconditioner: orbital-energy differences on the amplitude blocks
+        # preconditioner: maps a parameter-space residual to the constraint
+        # space of the multipliers, pairing t <-> Omega, (r0, R)_k <-> the
+        # eigenvalue rows of state k, E_k <-> its normalisation, zeta <-> O,
+        # scaled by orbital-energy differences (shifted by omega_k)
         dvec = self.P.denominators(s.eps)
-        prec = np.ones(nl)
-        prec[:self.na] = 1.0 / dvec
-        off = self.na + self.np_
+        na, np_ = self.na, self.np_
+        scale = np.ones(nl)
+        src = np.arange(nl)
+        scale[:na] = 1.0 / dvec
         for k in range(self.ns):
             om = s.E[k] - s.E0
             dk = np.concatenate([[-om], dvec - om])
             dk = np.where(np.abs(dk) < 0.05, np.sign(dk + 1e-300) * 0.05, dk)
-            prec[off:off + self.na + 1] = 1.0 / dk
-            off += self.na + 2
+            cs, ps = na + k * (na + 2), na + np_ + k * (na + 2)
+            scale[cs:cs + na + 1] = 1.0 / dk
+            src[cs:cs + na + 2] = np.arange(ps, ps + na + 2)
+        co = na + self.ns * (na + 2)
+        src[co:co + np_] = np.arange(na, na + np_)
+
+        def prec(vec):
+            return scale * vec[src]
         b = -c_lam.detach().numpy()
         if nl <= self.dense_limit:
             # small systems: the whole Jacobian, one row per constraint
@@ -457,9 +509,7 @@ class Lagrangian:
             x = np.linalg.solve(self._jac.T, b)
             info = "dense"
         else:
-            A = spla.LinearOperator((nl, nl), matvec=jt, dtype=np.float64)
-            Mp = spla.LinearOperator((nl, nl), matvec=lambda x: prec * x, dtype=np.float64)
-            x, info = spla.gmres(A, b, M=Mp, rtol=tol, atol=0.0, restart=400, maxiter=maxiter)
+            x, info = gmres(jt, prec, b, tol, maxiter)
         res = np.abs(jt(x) - b).max()
         if res > 1e3 * tol * max(1.0, np.abs(b).max()):
             raise RuntimeError(f"multiplier solve failed: residual {res:.2e}")

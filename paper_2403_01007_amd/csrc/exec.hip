@@ -248,7 +248,7 @@ static unsigned grid_for(int64_t n, int threads = 256) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
 }
 
-void launch_gemm(const GemmArgs& a, hipStream_t s) {
+void launch_gemm_main(const GemmArgs& a, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return;
   if (a.splits > 1 && (a.batch != 1 || !a.P || a.kchunk <= 0)) throw std::runtime_error("bad split-K plan");
   dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((a.M + BM - 1) / BM),
@@ -256,10 +256,33 @@ void launch_gemm(const GemmArgs& a, hipStream_t s) {
   if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm grid too large");
   hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(GEMM_THREADS), 0, s, a);
   check(hipGetLastError(), "gemm launch");
-  if (a.splits > 1) {
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(a.M * a.N)), dim3(256), 0, s, a);
-    check(hipGetLastError(), "split-K reduce launch");
+}
+
+void launch_gemm_reduce(const GemmArgs& a, hipStream_t s) {
+  if (a.splits <= 1 || a.M <= 0 || a.N <= 0) return;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(a.M * a.N)), dim3(256), 0, s, a);
+  check(hipGetLastError(), "split-K reduce launch");
+}
+
+void launch_gemm(const GemmArgs& a, hipStream_t s) {
+  launch_gemm_main(a, s);
+  launch_gemm_reduce(a, s);
+}
+
+__global__ void combine_kernel(const double* __restrict__ X, int k, int64_t n, const double* __restrict__ coef,
+                               double* __restrict__ y) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double acc = y[i];
+    for (int j = 0; j < k; ++j) acc += coef[j] * X[(int64_t)j * n + i];
+    y[i] = acc;
   }
+}
+
+void launch_combine(const double* X, int k, int64_t n, const double* coef, double* y, hipStream_t s) {
+  if (k <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(combine_kernel, dim3(grid_for(n)), dim3(256), 0, s, X, k, n, coef, y);
+  check(hipGetLastError(), "combine launch");
 }
 
 void launch_perm(const PermArgs& a, hipStream_t s) {
@@ -302,7 +325,8 @@ void launch_sym_pairs(double* x, int64_t nov, hipStream_t s) {
 void launch_deriv_contract(const double* dh, int64_t nh, const double* D1, const double* dL, int64_t nl,
                            const double* Z, int ncoord, double* grad, double* partials, hipStream_t s) {
   if (ncoord <= 0) return;
-  int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (nl + 256 * 64 - 1) / (256 * 64)));
+  int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (nh + nl + 256 * 64 - 1) / (256 * 64)));
+  while ((int64_t)chunks * ncoord > (1 << 18)) chunks /= 2;
   // partials must hold ncoord * chunks doubles
   hipLaunchKernelGGL(deriv_contract_kernel, dim3(chunks, ncoord), dim3(RED_THREADS), 0, s, dh, nh, D1, dL, nl, Z,
                      partials, chunks);
@@ -592,6 +616,7 @@ void Executor::set_profile(bool on) {
     ev_.resize(2 * 4096);
     for (auto& e : ev_) check(hipEventCreate(&e), "event create");
     ev_flops_.resize(4096);
+    ev_shape_.resize(4096);
   }
   if (!on) flush_profile();
   prof_ = on;
@@ -605,6 +630,10 @@ void Executor::flush_profile() {
     check(hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]), "event elapsed");
     gemm_ms += ms;
     gemm_flops += ev_flops_[i];
+    ShapeStat& st = shapes_[ev_shape_[i]];
+    st.n += 1;
+    st.ms += ms;
+    st.flops += ev_flops_[i];
   }
   gemm_launches += (int64_t)nev_;
   nev_ = 0;
@@ -612,11 +641,27 @@ void Executor::flush_profile() {
 
 void Executor::timed_gemm(const GemmArgs& g, hipStream_t s) {
   if (nev_ == ev_flops_.size()) flush_profile();
+  // the events bracket the MFMA kernel alone (a split-K reduction follows)
   check(hipEventRecord(ev_[2 * nev_], s), "event record");
-  launch_gemm(g, s);
+  launch_gemm_main(g, s);
   check(hipEventRecord(ev_[2 * nev_ + 1], s), "event record");
+  launch_gemm_reduce(g, s);
   ev_flops_[nev_] = 2.0 * g.M * g.N * g.K * g.batch;
+  ev_shape_[nev_] = {g.M, g.N, g.K, g.batch, g.splits};
   ++nev_;
+}
+
+void Executor::shape_report(FILE* f, int top) const {
+  std::vector<std::pair<std::array<int64_t, 5>, ShapeStat>> v(shapes_.begin(), shapes_.end());
+  std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
+  std::fprintf(f, "gemm shapes by time (M N K batch splits: launches, ms, TFLOP/s)\n");
+  for (int i = 0; i < (int)v.size() && i < top; ++i) {
+    const auto& k = v[i].first;
+    const auto& st = v[i].second;
+    std::fprintf(f, "  %7lld %7lld %7lld %4lld %3lld: %9lld %10.1f %6.2f\n", (long long)k[0], (long long)k[1],
+                 (long long)k[2], (long long)k[3], (long long)k[4], (long long)st.n, st.ms,
+                 st.ms > 0 ? st.flops / (st.ms * 1e9) : 0.0);
+  }
 }
 
 double Executor::flops(const std::vector<int>& list) const {
@@ -638,6 +683,7 @@ void Executor::run(const std::vector<int>& list, hipStream_t s) {
 
 void Executor::run_op(int k, hipStream_t s) {
   const Op& op = g_.ops[k];
+  if (g_.t[op.out].offset < 0) throw std::runtime_error("op without storage (not in any program)");
   switch (op.kind) {
     case OpKind::Contract: {
       const ContractPlan& p = plans_[k];

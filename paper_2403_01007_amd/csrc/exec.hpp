@@ -2,6 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -45,6 +48,11 @@ struct PermArgs {
 };
 
 void launch_gemm(const GemmArgs& a, hipStream_t s);
+// the MFMA kernel alone, and the split-K reduction that follows it
+void launch_gemm_main(const GemmArgs& a, hipStream_t s);
+void launch_gemm_reduce(const GemmArgs& a, hipStream_t s);
+// y[i] += sum_j coef[j] X[j][i] over X [k][n] (coef: device, k entries)
+void launch_combine(const double* X, int k, int64_t n, const double* coef, double* y, hipStream_t s);
 void launch_perm(const PermArgs& a, hipStream_t s);
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 // out[0] = alpha * sum x[i] y[i] + beta * addend[0]  (deterministic order);
@@ -85,6 +93,8 @@ class Executor {
   void flush_profile();
   double gemm_ms = 0.0, gemm_flops = 0.0;
   int64_t gemm_launches = 0;
+  // per-shape totals of the timed launches, largest time first
+  void shape_report(FILE* f, int top) const;
   ~Executor();
 
  private:
@@ -97,6 +107,12 @@ class Executor {
   bool prof_ = false;
   std::vector<hipEvent_t> ev_;
   std::vector<double> ev_flops_;
+  std::vector<std::array<int64_t, 5>> ev_shape_;
+  struct ShapeStat {
+    int64_t n = 0;
+    double ms = 0.0, flops = 0.0;
+  };
+  std::map<std::array<int64_t, 5>, ShapeStat> shapes_;
   size_t nev_ = 0;
   void run_op(int k, hipStream_t s);
   void timed_gemm(const GemmArgs& g, hipStream_t s);

@@ -290,6 +290,66 @@ std::map<int, int> Graph::vjp(int begin, int end, const std::map<int, int>& seed
   return out;
 }
 
+std::vector<int> Graph::batchify(const std::vector<int>& list, const std::vector<int>& inputs, int64_t nb,
+                                 std::map<int, int>& map) {
+  auto bdims = [&](int id) {
+    std::vector<int64_t> d = {nb};
+    for (auto x : dims(id)) d.push_back(x);
+    return d;
+  };
+  for (int in : inputs) map[in] = tensor(bdims(in), t[in].name + "[Z]");
+  auto B = [&](int id) -> int {
+    auto it = map.find(id);
+    return it == map.end() ? -1 : it->second;
+  };
+  size_t first = ops.size();
+  for (int k : list) {
+    const Op op = ops[k];  // copy: ops may reallocate
+    int res = -1;
+    switch (op.kind) {
+      case OpKind::Contract: {
+        int a = B(op.a), b = B(op.b), c0 = op.c0 >= 0 ? B(op.c0) : -1;
+        if (a < 0 && b < 0) continue;
+        if (a >= 0 && b >= 0) throw std::runtime_error("batchify: product of two batched tensors");
+        if (op.c0 >= 0 && c0 < 0) throw std::runtime_error("batchify: unbatched addend of a batched product");
+        std::string la = a >= 0 ? "Z" + op.la : op.la;
+        std::string lb = b >= 0 ? "Z" + op.lb : op.lb;
+        res = contract(la + "," + lb + "->Z" + op.lo, a >= 0 ? a : op.a, b >= 0 ? b : op.b, op.alpha,
+                       op.c0 >= 0 ? c0 : -1, op.beta);
+        break;
+      }
+      case OpKind::Lincomb: {
+        std::vector<Term> terms;
+        int nbat = 0;
+        for (size_t i = 0; i < op.ins.size(); ++i) {
+          int bi = B(op.ins[i]);
+          if (bi >= 0) {
+            ++nbat;
+            terms.push_back({op.coef[i], bi, "Z" + op.lin[i]});
+          }
+        }
+        if (nbat == 0) continue;
+        if (nbat != (int)op.ins.size()) throw std::runtime_error("batchify: mixed linear combination");
+        res = lincomb("Z" + op.lo, terms);
+        break;
+      }
+      case OpKind::Slice:
+      case OpKind::Embed: {
+        int a = B(op.a);
+        if (a < 0) continue;
+        std::vector<int64_t> off = {0};
+        for (int i = 0; i < t[op.a].nd; ++i) off.push_back(op.off[i]);
+        res = op.kind == OpKind::Slice ? slice(a, off, bdims(op.out)) : embed(a, off, bdims(op.out));
+        break;
+      }
+    }
+    map[op.out] = res;
+  }
+  std::vector<int> out;
+  for (size_t k = first; k < ops.size(); ++k) out.push_back((int)k);
+  return out;
+}
+
 std::vector<int> Graph::needed_ops(const std::vector<int>& outputs, const std::set<int>& have) const {
   std::vector<char> need(t.size(), 0);
   for (int o : outputs)
@@ -337,15 +397,99 @@ std::vector<int> Graph::dependent_ops(const std::vector<int>& list, const std::s
   return out;
 }
 
-int64_t Graph::finalize(int64_t align) {
-  int64_t pos = 0;
-  for (auto& d : t) {
-    if (d.zero) continue;
-    d.offset = pos;
-    int64_t s = d.size();
-    pos += (s + align - 1) / align * align;
+static std::vector<int> op_inputs(const Op& op) {
+  std::vector<int> r;
+  switch (op.kind) {
+    case OpKind::Contract:
+      r = {op.a, op.b};
+      if (op.c0 >= 0) r.push_back(op.c0);
+      break;
+    case OpKind::Lincomb:
+      r = op.ins;
+      break;
+    case OpKind::Slice:
+    case OpKind::Embed:
+      r = {op.a};
+      break;
   }
-  return pos;
+  return r;
+}
+
+int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, int64_t align) {
+  auto rnd = [&](int64_t n) { return (n + align - 1) / align * align; };
+  const int nt = (int)t.size();
+  // owner program of each tensor's producer and of each consumer (-2: several)
+  std::vector<int> prod_prog(nt, -1), use_prog(nt, -1), op_prog(ops.size(), -1);
+  for (int p = 0; p < (int)programs.size(); ++p)
+    for (int k : *programs[p]) op_prog[k] = op_prog[k] == -1 || op_prog[k] == p ? p : -2;
+  for (size_t k = 0; k < ops.size(); ++k) {
+    const int p = op_prog[k];
+    int& pp = prod_prog[ops[k].out];
+    pp = pp == -1 ? (p >= 0 ? p : -2) : -2;
+    for (int in : op_inputs(ops[k])) {
+      int& up = use_prog[in];
+      if (p < 0)
+        up = -2;
+      else
+        up = up == -1 || up == p ? p : -2;
+    }
+  }
+  std::vector<char> temp(nt, 0), dead(nt, 0);
+  for (size_t k = 0; k < ops.size(); ++k) {
+    // produced by an op no program runs: never computed, needs no storage
+    if (op_prog[k] == -1) dead[ops[k].out] = 1;
+  }
+  for (size_t k = 0; k < ops.size(); ++k)
+    if (op_prog[k] != -1)
+      for (int in : op_inputs(ops[k]))
+        if (dead[in]) throw std::runtime_error("a program reads a tensor no program computes");
+  for (int i = 0; i < nt; ++i) temp[i] = !t[i].zero && prod_prog[i] >= 0 && use_prog[i] == prod_prog[i];
+  // persistent storage
+  int64_t pos = 0;
+  for (int i = 0; i < nt; ++i) {
+    t[i].offset = -1;
+    if (t[i].zero || temp[i] || dead[i]) continue;
+    t[i].offset = pos;
+    pos += rnd(t[i].size());
+  }
+  // temporaries: liveness-based first fit within each program
+  const int64_t base = pos;
+  int64_t peak = 0;
+  for (int p = 0; p < (int)programs.size(); ++p) {
+    const auto& list = *programs[p];
+    std::map<int, int> last;
+    for (int j = 0; j < (int)list.size(); ++j)
+      for (int in : op_inputs(ops[list[j]]))
+        if (temp[in]) last[in] = j;
+    std::map<int64_t, int64_t> used;  // offset -> size, live blocks
+    std::vector<std::pair<int, int>> live;  // (last use, tensor)
+    for (int j = 0; j < (int)list.size(); ++j) {
+      // release temporaries whose last reader ran before op j
+      for (size_t q = 0; q < live.size();) {
+        if (live[q].first < j) {
+          used.erase(t[live[q].second].offset - base);
+          live[q] = live.back();
+          live.pop_back();
+        } else {
+          ++q;
+        }
+      }
+      const int out = ops[list[j]].out;
+      if (!temp[out] || prod_prog[out] != p) continue;
+      const int64_t need = rnd(t[out].size());
+      int64_t at = 0;
+      for (auto& b : used) {
+        if (b.first - at >= need) break;
+        at = std::max(at, b.first + b.second);
+      }
+      used[at] = need;
+      t[out].offset = base + at;
+      peak = std::max(peak, at + need);
+      auto it = last.find(out);
+      live.push_back({it == last.end() ? j : it->second, out});
+    }
+  }
+  return base + peak;
 }
 
 }  // namespace scc

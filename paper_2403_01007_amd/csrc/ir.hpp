@@ -91,6 +91,14 @@ class Graph {
   std::map<int, int> vjp(int begin, int end, const std::map<int, int>& seeds,
                          const std::vector<int>& wanted);
 
+  // Batch transform: copy the ops of `list` that depend on `inputs`, giving
+  // every tensor they produce a leading batch index of size nb (label 'Z').
+  // The programs transformed are linear in those inputs, so no op ever
+  // multiplies two batched tensors.  Returns the new op indices; `map` gets
+  // tensor -> batched tensor for the inputs and every transformed output.
+  std::vector<int> batchify(const std::vector<int>& list, const std::vector<int>& inputs, int64_t nb,
+                            std::map<int, int>& map);
+
   // Ops needed (within [0, ops.size())) to compute `outputs`, excluding any
   // op whose output is in `have` (already computed by an earlier phase).
   std::vector<int> needed_ops(const std::vector<int>& outputs,
@@ -99,7 +107,11 @@ class Graph {
   std::vector<int> dependent_ops(const std::vector<int>& list, const std::set<int>& vars) const;
 
   // Assign arena offsets to every non-zero tensor; returns doubles used.
-  int64_t finalize(int64_t align = 32);
+  // Tensors produced and consumed within a single program of `programs`
+  // (and read nowhere else) are temporaries: they share one region, reused
+  // within each program by liveness (programs run one at a time).  All
+  // other tensors get storage of their own.
+  int64_t finalize(const std::vector<const std::vector<int>*>& programs, int64_t align = 32);
 
  private:
   void check_labels(const std::string& l, int id, const char* what) const;

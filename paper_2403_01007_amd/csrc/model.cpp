@@ -237,8 +237,9 @@ std::set<int> outputs_of(const Graph& g, const std::vector<int>& list) {
 
 }  // namespace
 
-void build_model(Model& m, const Dims& d) {
+void build_model(Model& m, const Dims& d, int nb) {
   m.d = d;
+  m.nb = nb;
   Graph& g = m.g;
   const int64_t o = d.o, v = d.v, n = d.n, J = d.nj;
   const int ns = d.ns, np = d.npairs();
@@ -296,6 +297,17 @@ void build_model(Model& m, const Dims& d) {
     m.p_left = g.dependent_ops(all, {m.lin.r0, m.lin.r1, m.lin.r2});
     auto alld = g.needed_ops({m.dens_hk}, have);
     m.p_dens = g.dependent_ops(alld, {m.lin.r0, m.lin.r1, m.lin.r2, m.vin.r0, m.vin.r1, m.vin.r2});
+  }
+  // ---- batched right and left transformations
+  if (nb > 1) {
+    std::map<int, int> mp;
+    m.p_sigB = g.batchify(m.p_sig, {m.vin.r0, m.vin.r1, m.vin.r2}, nb, mp);
+    m.vinB = {mp.at(m.vin.r0), mp.at(m.vin.r1), mp.at(m.vin.r2)};
+    m.sigB = {mp.at(m.sig.s0), mp.at(m.sig.s1), mp.at(m.sig.s2)};
+    std::map<int, int> ml;
+    m.p_leftB = g.batchify(m.p_left, {m.lin.r0, m.lin.r1, m.lin.r2}, nb, ml);
+    m.linB = {ml.at(m.lin.r0), ml.at(m.lin.r1), ml.at(m.lin.r2)};
+    m.loutB = {ml.at(m.lout.r0), ml.at(m.lout.r1), ml.at(m.lout.r2)};
   }
   // ---- overlap of two states
   m.oa = new_state(g, d, "oa");
@@ -430,6 +442,14 @@ void build_model(Model& m, const Dims& d) {
                                     m.a_nac_r[k].r1, m.a_nac_r[k].r2},
                                    have));
   }
+}
+
+std::vector<const std::vector<int>*> programs(const Model& m) {
+  std::vector<const std::vector<int>*> r = {&m.p_setup, &m.p_res,      &m.p_sig_pre, &m.p_sig,   &m.p_left,
+                                            &m.p_ovl,   &m.p_dens,     &m.p_lag_pre, &m.p_lag,   &m.p_kappa,
+                                            &m.p_fk,    &m.p_integral, &m.p_sigB,    &m.p_leftB};
+  for (auto& p : m.p_nac) r.push_back(&p);
+  return r;
 }
 
 }  // namespace scc

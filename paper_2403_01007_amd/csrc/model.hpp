@@ -86,11 +86,20 @@ struct Model {
   std::vector<StateT> a_nac_r;          // per n
   std::vector<std::vector<int>> p_nac;  // per n
 
+  // --- right / left transformations of a block of nb vectors at once
+  //     (leading batch index on every input, output and intermediate)
+  int nb = 1;
+  StateT vinB{}, sigB{}, linB{}, loutB{};
+  std::vector<int> p_sigB, p_leftB;
+
   // op lists
   std::vector<int> p_setup, p_res, p_sig_pre, p_sig, p_left, p_ovl, p_dens, p_lag_pre, p_lag, p_kappa, p_fk,
       p_integral;
 };
 
-void build_model(Model& m, const Dims& d);
+void build_model(Model& m, const Dims& d, int nb = 1);
+
+// Every op list the context runs (the storage plan relies on this list).
+std::vector<const std::vector<int>*> programs(const Model& m);
 
 }  // namespace scc

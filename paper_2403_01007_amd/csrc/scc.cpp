@@ -58,7 +58,7 @@ Sizes sizes_for(const Dims& d) {
   s.nlag = s.nvt + d.ns * (s.nst + 1) + d.npairs();
   s.maxsub = std::max(40, 12 * d.ns + 24);
   int64_t p = 0;
-  p += up(s.nvt);                       // D
+  p += up(s.nvt) + up(s.nov);           // D, Dk
   p += 2 * d.ns * up(s.nst);            // R, L
   p += 2 * NDIIS * up(s.nvt) + 3 * up(s.nvt);
   p += 2 * s.maxsub * up(s.nvt) + 6 * (d.ns + 2) * up(s.nvt) + 2 * up(s.nvt);
@@ -98,13 +98,15 @@ struct scc_ctx {
   scc_options opt{};
   std::string err;
   // persistent device vectors
-  double* D = nullptr;        // orbital-energy denominators [nov | nov^2]
+  double* D = nullptr;        // diagonal preconditioner of the CC blocks [nov | nov^2]
+  double* Dk = nullptr;       // diagonal of the orbital Hessian [nov]
   std::vector<double*> R, Lv; // states [r0 | r1 | r2]
   double* kbar = nullptr;
   double* dsc = nullptr;      // device scalars
   Recycler rec_lag, rec_k;    // recycled Krylov spaces of the multiplier solves
   std::vector<double> eps;
   bool have_h = false, have_ground = false, have_excited = false, have_mult = false;
+  bool scc_on = false;        // the SCC constraint (zeta, O_kl) is part of the solution
   double E0 = 0.0, enuc = 0.0;
   std::vector<double> E, zeta;
   int mult_kind = -1, mult_m = -1, mult_n = -1;
@@ -258,6 +260,28 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
   return SCC_OK;
 }
 
+// out[i] = C[i] . r for i < k (host copy returned)
+std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, const double* r) {
+  std::vector<double> h(k);
+  if (k == 0) return h;
+  double* dout = c->dsc + 16;
+  double* tmp = c->alloc(k);
+  launch_deriv_contract(Cb, n, r, Cb, 0, r, k, tmp, c->partials, c->s);
+  c->sync();
+  hck(hipMemcpy(h.data(), tmp, k * sizeof(double), hipMemcpyDeviceToHost));
+  c->pool_used -= up(k);
+  (void)dout;
+  return h;
+}
+
+// y += sum_i coef_i X[i] (X [k][n]) in one streaming pass
+void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* devcoef,
+                double* y) {
+  if (k == 0) return;
+  hck(hipMemcpyAsync(devcoef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice, c->s));
+  launch_combine(Xb, k, n, devcoef, y, c->s);
+}
+
 // ---------------------------------------------------------------------------
 // nonsymmetric Davidson on the excited-excited block (r0 = 0): right
 // eigenvectors of Hbar (left = false) or of Hbar^T (left = true)
@@ -283,6 +307,40 @@ void apply_block(scc_ctx* c, bool left, const double* v, double* w) {
   c->sym_doubles(w + nov);
 }
 
+// w_i = A v_i for i < cnt through the batched programs (nb vectors a pass)
+void apply_many(scc_ctx* c, bool left, double* const* v, double* const* w, int cnt) {
+  Model& m = c->m;
+  const int64_t nov = c->sz.nov, n2 = nov * nov;
+  const int nb = m.nb;
+  if (nb <= 1) {
+    for (int i = 0; i < cnt; ++i) apply_block(c, left, v[i], w[i]);
+    return;
+  }
+  const StateT& in = left ? m.linB : m.vinB;
+  const StateT& out = left ? m.loutB : m.sigB;
+  for (int b0 = 0; b0 < cnt; b0 += nb) {
+    const int nc = std::min(nb, cnt - b0);
+    c->fill(c->tp(in.r0), nb, 0.0);
+    for (int j = 0; j < nb; ++j) {
+      double* r1 = c->tp(in.r1) + j * nov;
+      double* r2 = c->tp(in.r2) + j * n2;
+      if (j < nc) {
+        c->cp(r1, v[b0 + j], nov);
+        c->cp(r2, v[b0 + j] + nov, n2);
+      } else {
+        c->fill(r1, nov, 0.0);
+        c->fill(r2, n2, 0.0);
+      }
+    }
+    c->run(left ? m.p_leftB : m.p_sigB);
+    for (int j = 0; j < nc; ++j) {
+      c->cp(w[b0 + j], c->tp(out.r1) + j * nov, nov);
+      c->cp(w[b0 + j] + nov, c->tp(out.r2) + j * n2, n2);
+      c->sym_doubles(w[b0 + j] + nov);
+    }
+  }
+}
+
 int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>& guess, double tol, int maxit,
              std::vector<double>& evals, std::vector<double*>& out, int& iters) {
   const int64_t nvt = c->sz.nvt, nov = c->sz.nov;
@@ -295,10 +353,13 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
   const double pfloor = 0.05;
   int64_t mark = c->pool_used;
   std::vector<double*> V(maxsub), W(maxsub);
+  double* Vb = c->alloc((int64_t)maxsub * nvt);
+  double* Wb = c->alloc((int64_t)maxsub * nvt);
   for (int i = 0; i < maxsub; ++i) {
-    V[i] = c->alloc(nvt);
-    W[i] = c->alloc(nvt);
+    V[i] = Vb + (int64_t)i * nvt;
+    W[i] = Wb + (int64_t)i * nvt;
   }
+  double* dcoef = c->alloc(maxsub);
   std::vector<double*> Xr(nkeep), Xw(nkeep), Rs(nwork);
   for (int i = 0; i < nkeep; ++i) {
     Xr[i] = c->alloc(nvt);
@@ -311,11 +372,11 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     double n0 = std::sqrt(c->dot(src, src, nvt));
     if (!(n0 > 0)) return false;
     c->axpby(0.0, src, 1.0 / n0, src, nvt);
-    for (int pass = 0; pass < 2; ++pass)
-      for (int j = 0; j < nv; ++j) {
-        double h = c->dot(V[j], src, nvt);
-        c->axpby(-h, V[j], 1.0, src, nvt);
-      }
+    for (int pass = 0; pass < 2; ++pass) {
+      auto h = multi_dot(c, Vb, nv, nvt, src);
+      for (auto& x : h) x = -x;
+      multi_axpy(c, Vb, nv, nvt, h, dcoef, src);
+    }
     double nr = std::sqrt(c->dot(src, src, nvt));
     if (nr < 1e-8) return false;
     c->cp(V[nv], src, nvt);
@@ -346,10 +407,19 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
   iters = 0;
   for (int it = 0; it < maxit; ++it) {
     iters = it + 1;
-    for (; nw < nv; ++nw) apply_block(c, left, V[nw], W[nw]);
-    for (int i = 0; i < nv; ++i)
-      for (int j = 0; j < nv; ++j)
-        if (i >= ng || j >= ng) G[i * maxsub + j] = c->dot(V[i], W[j], nvt);
+    if (nw < nv) {
+      apply_many(c, left, &V[nw], &W[nw], nv - nw);
+      nw = nv;
+    }
+    // new rows and columns of the subspace matrix G_ij = V_i . W_j
+    for (int j = ng; j < nv; ++j) {
+      auto col = multi_dot(c, Vb, nv, nvt, W[j]);
+      for (int i = 0; i < nv; ++i) G[i * maxsub + j] = col[i];
+    }
+    for (int i = ng; i < nv; ++i) {
+      auto row = multi_dot(c, Wb, ng, nvt, V[i]);
+      for (int j = 0; j < ng; ++j) G[i * maxsub + j] = row[j];
+    }
     ng = nv;
     std::vector<double> Gs(nv * nv);
     for (int i = 0; i < nv; ++i)
@@ -379,10 +449,9 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       yn = std::sqrt(yn);
       c->fill(Xr[k], nvt, 0.0);
       c->fill(Xw[k], nvt, 0.0);
-      for (int j = 0; j < nv; ++j) {
-        c->axpby(y[j] / yn, V[j], 1.0, Xr[k], nvt);
-        c->axpby(y[j] / yn, W[j], 1.0, Xw[k], nvt);
-      }
+      for (auto& yy : y) yy /= yn;
+      multi_axpy(c, Vb, nv, nvt, y, dcoef, Xr[k]);
+      multi_axpy(c, Wb, nv, nvt, y, dcoef, Xw[k]);
       if (k < nr_now) {
         c->cp(Rs[k], Xw[k], nvt);
         c->axpby(-th[k], Xr[k], 1.0, Rs[k], nvt);
@@ -411,12 +480,12 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       // thick restart on the lowest nkeep Ritz vectors (orthonormalised)
       nv = 0;
       for (int k = 0; k < nx; ++k) {
-        for (int pass = 0; pass < 2; ++pass)
-          for (int j = 0; j < nv; ++j) {
-            double h = c->dot(V[j], Xr[k], nvt);
-            c->axpby(-h, V[j], 1.0, Xr[k], nvt);
-            c->axpby(-h, W[j], 1.0, Xw[k], nvt);
-          }
+        for (int pass = 0; pass < 2; ++pass) {
+          auto h = multi_dot(c, Vb, nv, nvt, Xr[k]);
+          for (auto& x : h) x = -x;
+          multi_axpy(c, Vb, nv, nvt, h, dcoef, Xr[k]);
+          multi_axpy(c, Wb, nv, nvt, h, dcoef, Xw[k]);
+        }
         double nr = std::sqrt(c->dot(Xr[k], Xr[k], nvt));
         if (nr < 1e-8) continue;
         c->cp(V[nv], Xr[k], nvt);
@@ -451,7 +520,7 @@ double state_overlap(scc_ctx* c, const double* a, const double* b) {
   return c->tensor_scalar(m.ovl);
 }
 
-int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& iters) {
+int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& iters, bool need_left = true) {
   Model& m = c->m;
   const int ns = c->m.d.ns;
   const int64_t nvt = c->sz.nvt, nov = c->sz.nov, nst = c->sz.nst;
@@ -481,12 +550,14 @@ int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& ite
   int itR = 0, itL = 0;
   rc = davidson(c, false, ns, gr, tol, maxit, ER, oR, itR);
   if (rc) return rc;
-  rc = davidson(c, true, ns, gl, tol, maxit, EL, oL, itL);
-  if (rc) return rc;
+  if (need_left) {
+    rc = davidson(c, true, ns, gl, tol, maxit, EL, oL, itL);
+    if (rc) return rc;
+  }
   iters += itR + itL;
   c->E.assign(ns, 0.0);
   for (int k = 0; k < ns; ++k) {
-    if (std::fabs(ER[k] - EL[k]) > 1e-6 * std::max(1.0, std::fabs(ER[k])))
+    if (need_left && std::fabs(ER[k] - EL[k]) > 1e-6 * std::max(1.0, std::fabs(ER[k])))
       throw SccError(SCC_ENOCONV, "left and right excitation energies differ");
     c->E[k] = ER[k];
     double om = ER[k] - c->E0;
@@ -502,7 +573,7 @@ int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& ite
     c->axpby(0.0, outR[k], 1.0 / std::sqrt(okk), outR[k], nst);
     // phase
     if (warm) {
-      double ov = c->dot(c->Lv[k], outR[k], nst);
+      double ov = c->dot(c->R[k], outR[k], nst);
       if (ov < 0) c->axpby(0.0, outR[k], -1.0, outR[k], nst);
     } else {
       std::vector<double> r1(nov);
@@ -513,14 +584,16 @@ int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& ite
         if (std::fabs(r1[i]) > std::fabs(r1[im])) im = i;
       if (r1[im] < 0) c->axpby(0.0, outR[k], -1.0, outR[k], nst);
     }
-    // L0 = 0, L.R = 1
-    c->fill(outL[k], 1, 0.0);
-    double lr = c->dot(outL[k], outR[k], nst);
-    c->axpby(0.0, outL[k], 1.0 / lr, outL[k], nst);
+    if (need_left) {
+      // L0 = 0, L.R = 1
+      c->fill(outL[k], 1, 0.0);
+      double lr = c->dot(outL[k], outR[k], nst);
+      c->axpby(0.0, outL[k], 1.0 / lr, outL[k], nst);
+    }
   }
   for (int k = 0; k < ns; ++k) {
     c->cp(c->R[k], outR[k], nst);
-    c->cp(c->Lv[k], outL[k], nst);
+    if (need_left) c->cp(c->Lv[k], outL[k], nst);
   }
   c->pool_used = mark;
   (void)nvt;
@@ -549,9 +622,12 @@ int excited_solve(scc_ctx* c, scc_info* info) {
   int iters = 0;
   c->zeta.assign(np, 0.0);
   set_scc_inputs(c, c->zeta, false);
-  int rc = excited_at_fixed_zeta(c, tol, maxit, false, iters);
-  if (rc) return rc;
   const bool use_scc = c->opt.scc && c->m.d.o >= 2 && np > 0;
+  c->scc_on = use_scc;
+  // with the constraint active, the CCSD states are only the starting point:
+  // left vectors are solved once, at the converged SCC point
+  int rc = excited_at_fixed_zeta(c, tol, maxit, false, iters, !use_scc);
+  if (rc) return rc;
   if (use_scc) {
     const int64_t nst = c->sz.nst;
     int64_t mark = c->pool_used;
@@ -560,10 +636,15 @@ int excited_solve(scc_ctx* c, scc_info* info) {
     std::vector<double> Jz;
     std::vector<double> z = c->zeta, Oprev, zprev;
     bool conv = false;
+    double omax_prev = 1.0;
     for (int it = 0; it < c->opt.max_iter && !conv; ++it) {
+      // inexact inner solves while the constraint is far from satisfied
+      // (the first pass, at zeta = 0 from converged CCSD states, is tight: it
+      // is the base point of the finite-difference Jacobian)
+      const double tol_it = it == 0 ? tol : std::max(tol, std::min(1e-5, 1e-3 * omax_prev));
       for (int k = 0; k < ns; ++k) c->cp(prev[k], c->R[k], nst);
       set_scc_inputs(c, z, true);
-      rc = excited_at_fixed_zeta(c, tol, maxit, true, iters);
+      rc = excited_at_fixed_zeta(c, tol_it, maxit, true, iters, false);
       if (rc) return rc;
       std::vector<double> O = pair_overlaps(c);
       double dR = 0, omax = 0;
@@ -575,15 +656,16 @@ int excited_solve(scc_ctx* c, scc_info* info) {
         c->pool_used -= up(nst);
       }
       for (double x : O) omax = std::max(omax, std::fabs(x));
-      c->log(" scc it %2d  max|O| %.3e  |dR| %.3e  zeta0 %.8f\n", it, omax, dR, z[0]);
-      if (omax < c->opt.tol_overlap && dR < 10 * tol) {
+      c->log(" scc it %2d  max|O| %.3e  |dR| %.3e  zeta0 %.8f  (inner tol %.1e)\n", it, omax, dR, z[0], tol_it);
+      omax_prev = omax;
+      if (omax < c->opt.tol_overlap && dR < 10 * tol && tol_it <= tol) {
         conv = true;
         break;
       }
       if (Jz.empty()) {
         // finite-difference Jacobian dO/dzeta with the X3 states held fixed
         Jz.assign(np * np, 0.0);
-        const double h = 1e-5;
+        const double h = 1e-4;
         std::vector<double*> keepR(ns), keepL(ns);
         for (int k = 0; k < ns; ++k) {
           keepR[k] = c->alloc(nst);
@@ -595,7 +677,7 @@ int excited_solve(scc_ctx* c, scc_info* info) {
           std::vector<double> zp = z;
           zp[p] += h;
           set_scc_inputs(c, zp, false);
-          rc = excited_at_fixed_zeta(c, tol, maxit, true, iters);
+          rc = excited_at_fixed_zeta(c, tol_it, maxit, true, iters, false);
           if (rc) return rc;
           std::vector<double> Op = pair_overlaps(c);
           for (int q = 0; q < np; ++q) Jz[q * np + p] = (Op[q] - O[q]) / h;
@@ -630,6 +712,12 @@ int excited_solve(scc_ctx* c, scc_info* info) {
     c->pool_used = mark;
     c->zeta = z;
     if (!conv) return SCC_ENOCONV;
+    // left eigenvectors once, at the converged (zeta, X3) point, started
+    // from the right vectors
+    set_scc_inputs(c, z, false);
+    for (int k = 0; k < ns; ++k) c->cp(c->Lv[k], c->R[k], nst);
+    rc = excited_at_fixed_zeta(c, tol, maxit, true, iters, true);
+    if (rc) return rc;
   }
   if (info) {
     info->iterations = iters;
@@ -731,45 +819,6 @@ int gmres(scc_ctx* c, int64_t n, const LinOp& A, const LinOp& Minv, const double
 // right-hand sides of the same operator (all gradient / coupling targets share
 // the Lagrangian Jacobian).  Equivalent to unrestarted GMRES for one RHS.
 // ---------------------------------------------------------------------------
-// out[i] = C[i] . r for i < k (host copy returned)
-std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, const double* r) {
-  std::vector<double> h(k);
-  if (k == 0) return h;
-  double* dout = c->dsc + 16;
-  double* tmp = c->alloc(k);
-  launch_deriv_contract(Cb, n, r, Cb, 0, r, k, tmp, c->partials, c->s);
-  c->sync();
-  hck(hipMemcpy(h.data(), tmp, k * sizeof(double), hipMemcpyDeviceToHost));
-  c->pool_used -= up(k);
-  (void)dout;
-  return h;
-}
-
-// y += sum_i coef_i X[i] (X [k][n]) as one GEMV on the matrix cores
-void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* devcoef,
-                double* y) {
-  if (k == 0) return;
-  hck(hipMemcpyAsync(devcoef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice, c->s));
-  GemmArgs g{};
-  g.M = n;
-  g.N = 1;
-  g.K = k;
-  g.batch = 1;
-  g.alpha = 1.0;
-  g.beta = 1.0;
-  g.A = Xb;
-  g.sAm = 1;
-  g.sAk = n;
-  g.B = devcoef;
-  g.sBk = 1;
-  g.sBn = 0;
-  g.Cin = y;
-  g.C = y;
-  g.sCm = 1;
-  g.sCn = 0;
-  launch_gemm(g, c->s);
-}
-
 int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const double* b, double* x, double tol,
         int maxit, int& iters, double& relres) {
   const int64_t n = rc.n;
@@ -884,6 +933,7 @@ struct Seg {
   int64_t n;
   int kind;   // 0: t block, 1+k: state k block, -1: E / zeta
   int comp;   // 0 scalar, 1 singles, 2 doubles
+  bool active = true;  // false: zeta / O_kl of a solution without the SCC constraint
 };
 
 std::vector<Seg> lag_segments(scc_ctx* c) {
@@ -898,7 +948,7 @@ std::vector<Seg> lag_segments(scc_ctx* c) {
     s.push_back({m.mk[k].s2, m.a_r[k].r2, nov * nov, 1 + k, 2});
     s.push_back({m.mN[k], m.a_E[k], 1, -1, 0});
   }
-  for (int p = 0; p < m.d.npairs(); ++p) s.push_back({m.mO[p], m.a_z[p], 1, -1, 0});
+  for (int p = 0; p < m.d.npairs(); ++p) s.push_back({m.mO[p], m.a_z[p], 1, -1, 0, c->scc_on});
   return s;
 }
 
@@ -963,6 +1013,10 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   auto prec = [&](const double* in, double* out) {
     for (size_t i = 0; i < segs.size(); ++i) {
       const Seg& sg = segs[i];
+      if (!sg.active) {
+        c->fill(out + offs[i], sg.n, 0.0);
+        continue;
+      }
       if (sg.kind < 0) {
         c->cp(out + offs[i], in + offs[i], sg.n);
         continue;
@@ -973,9 +1027,18 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
     }
   };
   auto apply = [&](const double* in, double* out) {
-    for (size_t i = 0; i < segs.size(); ++i) c->put(segs[i].mult, in + offs[i]);
+    for (size_t i = 0; i < segs.size(); ++i) {
+      if (segs[i].active)
+        c->put(segs[i].mult, in + offs[i]);
+      else
+        c->fill(c->tp(segs[i].mult), segs[i].n, 0.0);
+    }
     c->run(m.p_lag);
     for (size_t i = 0; i < segs.size(); ++i) {
+      if (!segs[i].active) {
+        c->fill(out + offs[i], segs[i].n, 0.0);
+        continue;
+      }
       c->get(segs[i].adj, out + offs[i]);
       if (segs[i].comp == 2) c->sym_doubles(out + offs[i]);
     }
@@ -989,7 +1052,12 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
     return rc;
   }
   // leave the multipliers in their tensors
-  for (size_t i = 0; i < segs.size(); ++i) c->put(segs[i].mult, x + offs[i]);
+  for (size_t i = 0; i < segs.size(); ++i) {
+    if (segs[i].active)
+      c->put(segs[i].mult, x + offs[i]);
+    else
+      c->fill(c->tp(segs[i].mult), segs[i].n, 0.0);
+  }
   // orbital multipliers: A_HF^T kbar = -(eta_kappa + dTarget/dkappa)
   c->fill(c->tp(m.mF), nov, 0.0);
   c->run(m.p_kappa);
@@ -1018,9 +1086,7 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
     c->run(m.p_fk);
     c->get(m.fk_adj, out);
   };
-  double* Dk = c->alloc(nov);
-  c->cp(Dk, c->D, nov);
-  auto precF = [&](const double* in, double* out) { launch_precond(in, Dk, 0.0, 1e-3, out, nov, c->s); };
+  auto precF = [&](const double* in, double* out) { launch_precond(in, c->Dk, 0.0, 1e-3, out, nov, c->s); };
   c->fill(c->kbar, nov, 0.0);
   int itk = 0;
   double relk = 0;
@@ -1101,8 +1167,8 @@ Plan make_plan(const scc_dims* d) {
   Plan p;
   p.m = std::make_unique<Model>();
   Dims dd{d->nocc, d->nvirt, d->nocc + d->nvirt, d->nchol, d->nstates};
-  build_model(*p.m, dd);
-  p.arena = up(p.m->g.finalize(), 32);
+  build_model(*p.m, dd, dd.ns + 2);
+  p.arena = up(p.m->g.finalize(programs(*p.m)), 32);
   p.scratch = up(std::max<int64_t>(Executor::plan_scratch(p.m->g), 32));
   p.pool = up(sizes_for(dd).pool);
   p.bytes = (size_t)(p.arena + p.scratch + PARTIALS + p.pool) * sizeof(double) + 256;
@@ -1151,6 +1217,7 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     c->ex = std::make_unique<Executor>(c->m.g, c->arena, c->scratch, c->scratch_n, c->partials);
     c->ex->plan_all();
     c->D = c->alloc(c->sz.nvt);
+    c->Dk = c->alloc(c->sz.nov);
     for (int k = 0; k < dd.ns; ++k) {
       c->R.push_back(c->alloc(c->sz.nst));
       c->Lv.push_back(c->alloc(c->sz.nst));
@@ -1202,6 +1269,8 @@ const char* scc_last_error(const scc_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int scc_set_hamiltonian(scc_ctx* c, const double* h, const double* chol, double e_nuc) {
   if (!c || !h || !chol) return SCC_EINVAL;
+  // a failed call leaves the context without a Hamiltonian
+  c->have_h = c->have_ground = c->have_excited = c->have_mult = false;
   return guarded(c, nullptr, [&]() -> int {
     Model& m = c->m;
     c->cp(c->tp(m.h), h, m.g.t[m.h].size());
@@ -1219,13 +1288,39 @@ int scc_set_hamiltonian(scc_ctx* c, const double* h, const double* chol, double 
     for (int a = 0; a < v; ++a)
       for (int i = 0; i < o; ++i) fai = std::max(fai, std::fabs(F[(size_t)(o + a) * N + i]));
     if (fai > 1e-6) throw SccError(SCC_EINVAL, "integrals are not in a Hartree-Fock basis (max|F_ai| > 1e-6)");
-    std::vector<double> D(c->sz.nvt);
+    // Diagonal preconditioners.  Doubles: orbital-energy differences.
+    // Singles: the diagonal of the singlet singles-singles block at t = 0,
+    //   eps_a - eps_i + 2 (ai|ai) - (aa|ii),
+    // which differs from eps_a - eps_i by terms of the size of the low
+    // excitation energies themselves.  Orbital response: the diagonal of
+    // the closed-shell RHF Hessian, eps_a - eps_i + 3 (ai|ai) - (aa|ii).
+    const int J = m.d.nj;
+    std::vector<double> Lh((size_t)J * N * N);
+    hck(hipMemcpy(Lh.data(), c->tp(m.L), Lh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> D(c->sz.nvt), Dk(c->sz.nov);
     const int64_t nov = c->sz.nov;
     for (int a = 0; a < v; ++a)
-      for (int i = 0; i < o; ++i) D[a * o + i] = c->eps[o + a] - c->eps[i];
-    for (int64_t p = 0; p < nov; ++p)
-      for (int64_t q = 0; q < nov; ++q) D[nov + p * nov + q] = D[p] + D[q];
+      for (int i = 0; i < o; ++i) {
+        double coul = 0, exch = 0;
+        for (int j = 0; j < J; ++j) {
+          const double* Lj = Lh.data() + (size_t)j * N * N;
+          double lai = Lj[(size_t)(o + a) * N + i];
+          coul += lai * lai;
+          exch += Lj[(size_t)(o + a) * N + o + a] * Lj[(size_t)i * N + i];
+        }
+        const double de = c->eps[o + a] - c->eps[i];
+        D[a * o + i] = de + 2.0 * coul - exch;
+        Dk[a * o + i] = de + 3.0 * coul - exch;
+      }
+    for (int64_t p = 0; p < nov; ++p) {
+      const int64_t ap = p / o, ip = p % o;
+      for (int64_t q = 0; q < nov; ++q) {
+        const int64_t aq = q / o, iq = q % o;
+        D[nov + p * nov + q] = c->eps[o + ap] - c->eps[ip] + c->eps[o + aq] - c->eps[iq];
+      }
+    }
     hck(hipMemcpy(c->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
+    hck(hipMemcpy(c->Dk, Dk.data(), Dk.size() * sizeof(double), hipMemcpyHostToDevice));
     // every geometry starts cold: t = 0 (the first Jacobi step is MP2), zeta = 0
     c->fill(c->tp(m.t1), nov, 0.0);
     c->fill(c->tp(m.t2), nov * nov, 0.0);
@@ -1271,7 +1366,10 @@ int scc_excited(scc_ctx* c, int nstates, const double* guess, double* energies, 
     c->err = "nstates must equal the context's nstates";
     return SCC_EINVAL;
   }
-  if (!c->have_h) return SCC_ESTATE;
+  if (!c->have_h) {
+    c->err = "scc_excited before scc_set_hamiltonian";
+    return SCC_ESTATE;
+  }
   (void)guess;
   return guarded(c, info, [&]() -> int {
     int rc = excited_solve(c, info);
@@ -1318,9 +1416,20 @@ int scc_densities(scc_ctx* c, double* d1, double* z3, double* kappa_bar) {
 
 static int derivative(scc_ctx* c, int kind, int mm, int nn, int ncoord, const double* dh, const double* dchol,
                       double* out, scc_info* info) {
-  if (!c || !dh || !dchol || !out || ncoord < 0) return SCC_EINVAL;
-  if ((int64_t)ncoord * 256 > PARTIALS) return SCC_EINVAL;
-  if (!c->have_excited) return SCC_ESTATE;
+  if (!c) return SCC_EINVAL;
+  const int ns = c->m.d.ns;
+  if (!dh || !dchol || !out || ncoord < 0 || (int64_t)ncoord * 256 > PARTIALS) {
+    c->err = "bad derivative-integral arguments";
+    return SCC_EINVAL;
+  }
+  if (nn < 0 || nn >= ns || (kind == 1 && (mm < 0 || mm >= ns || mm == nn))) {
+    c->err = "bad target state";
+    return SCC_EINVAL;
+  }
+  if (!c->have_excited) {
+    c->err = "gradient or coupling before scc_excited";
+    return SCC_ESTATE;
+  }
   return guarded(c, info, [&]() -> int {
     if (!(c->have_mult && c->mult_kind == kind && c->mult_n == nn && (kind == 0 || c->mult_m == mm))) {
       int rc = multipliers_solve(c, kind, mm, nn, info);
@@ -1379,6 +1488,7 @@ int scc_profile(scc_ctx* c, int enable, double* gemm_ms, double* gemm_flops, lon
   return guarded(c, nullptr, [&]() -> int {
     c->ex->flush_profile();
     c->ex->set_profile(enable != 0);
+    if (!enable && c->opt.verbose) c->ex->shape_report(stderr, 25);
     if (gemm_ms) *gemm_ms = c->ex->gemm_ms;
     if (gemm_flops) *gemm_flops = c->ex->gemm_flops;
     if (gemm_launches) *gemm_launches = (long long)c->ex->gemm_launches;

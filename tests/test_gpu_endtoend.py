@@ -1,0 +1,154 @@
+"""End-to-end GPU parity through the C ABI: energies, zeta, gradients of every
+state and couplings (both orders) against the FP64 oracle.
+
+Tolerances are those the method is held to: 1e-10 Eh in energies and 1e-8 in
+gradients and couplings (absolute, in Hartree per unit coordinate).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth_inputs import make_system
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+E_TOL, G_TOL = 1e-10, 1e-8
+
+
+def _run_gpu(S, scc=True, tol=1e-11):
+    from paper_2403_01007_amd import Context
+    h, L = S.at(np.zeros(S.ncoord))
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=tol, tol_overlap=1e-12, scc=scc)
+    ctx.set_hamiltonian(h, L)
+    E, z, _ = ctx.excited()
+    e0 = float(ctx.get(3).cpu()[0])
+    grads = {k: ctx.gradient(k, S.dh, S.dL)[0] for k in range(S.nstates)}
+    nacs = {}
+    for (m, n) in S.nacs:
+        nacs[(m, n)] = ctx.nac(m, n, S.dh, S.dL)[0]
+        nacs[(n, m)] = ctx.nac(n, m, S.dh, S.dL)[0]
+    return ctx, e0, E, z, grads, nacs
+
+
+def _compare(S, gpu, E0, E, zeta, grads, nacs, ztol=1e-7):
+    _, e0, Eg, zg, gg, ng = gpu
+    assert abs(e0 - E0) < E_TOL
+    assert np.abs(np.asarray(Eg) - np.asarray(E)).max() < E_TOL
+    if len(zeta):
+        assert np.abs(np.asarray(zg) - np.asarray(zeta)).max() < ztol
+    for k, ref in grads.items():
+        err = np.abs(gg[k] - np.asarray(ref)).max()
+        print(f"  grad {k} max err {err:.2e}", flush=True)
+        assert err < G_TOL
+    for key, ref in nacs.items():
+        err = np.abs(ng[key] - np.asarray(ref)).max()
+        print(f"  nac {key} max err {err:.2e}", flush=True)
+        assert err < G_TOL
+
+
+@pytest.mark.parametrize("scc", [True, False], ids=["sccsd", "ccsd"])
+def test_o2v4_against_live_oracle(scc):
+    from oracle import scc as oscc
+    S = make_system("o2v4")
+    print(f"[o2v4 scc={scc}]", flush=True)
+    gpu = _run_gpu(S, scc=scc)
+    sol = oscc.solve_system(S, scc=scc)
+    targets = [("grad", k) for k in range(S.nstates)]
+    for (m, n) in S.nacs:
+        targets += [("nac", m, n), ("nac", n, m)]
+    ref = oscc.gradient_and_nacs(S, sol, targets)
+    grads = {k: ref[("grad", k)]["value"] for k in range(S.nstates)}
+    nacs = {}
+    for (m, n) in S.nacs:
+        nacs[(m, n)] = ref[("nac", m, n)]["value"]
+        nacs[(n, m)] = ref[("nac", n, m)]["value"]
+    zeta = np.asarray(sol.zeta) if scc else []
+    if not scc:
+        assert np.all(gpu[3] == 0.0)
+    _compare(S, gpu, sol.E0, sol.E, zeta, grads, nacs)
+
+
+def test_o4v12_against_stored_oracle():
+    """o4v12 (two states, SCC active) against values written by
+    tests/golden/make_golden.py, which calls only the oracle."""
+    with open(os.path.join(HERE, "golden", "o4v12.json")) as f:
+        ref = json.load(f)
+    S = make_system("o4v12")
+    assert (S.seed, S.reading, S.o, S.v, S.nj) == (ref["seed"], ref["reading"], ref["o"], ref["v"], ref["nj"])
+    print("[o4v12 golden]", flush=True)
+    gpu = _run_gpu(S)
+    grads = {int(k): v for k, v in ref["grad"].items()}
+    nacs = {tuple(int(x) for x in k.split(",")): v for k, v in ref["nac"].items()}
+    _compare(S, gpu, ref["E0"], ref["E"], ref["zeta"], grads, nacs)
+
+
+def test_two_electron_exact():
+    """Two electrons: CCSD is exact, SCC is inactive (no triples), so the
+    energies are singlet FCI eigenvalues, the gradients Hellmann-Feynman
+    expectation values and the couplings <m|H1|n>/(E_n - E_m)."""
+    from oracle.fockspace import FockSpace, singlet_fci
+    S = make_system("o1v5")
+    print("[o1v5]", flush=True)
+    h, L = S.at(np.zeros(S.ncoord))
+    g = np.einsum("Jpq,Jrs->pqrs", L, L)
+    fs = FockSpace(S.o + S.v, S.o)
+    w, U = singlet_fci(fs, fs.hamiltonian(h, g), 1 + S.nstates)
+    ctx, e0, E, z, grads, nacs = _run_gpu(S)
+    assert abs(e0 - w[0]) < E_TOL
+    assert np.abs(np.asarray(E) - w[1:1 + S.nstates]).max() < E_TOL
+    for c in range(S.ncoord):
+        g1 = np.einsum("Jpq,Jrs->pqrs", S.dL[c], L) + np.einsum("Jpq,Jrs->pqrs", L, S.dL[c])
+        H1 = fs.hamiltonian(S.dh[c], g1)
+        for k in range(S.nstates):
+            ref = U[:, 1 + k] @ H1 @ U[:, 1 + k]
+            assert abs(grads[k][c] - ref) < G_TOL
+        for (m, n) in S.nacs:
+            ref = U[:, 1 + m] @ H1 @ U[:, 1 + n] / (w[1 + n] - w[1 + m])
+            # the FCI vectors carry arbitrary signs: compare magnitudes, and
+            # the exact antisymmetry of the couplings
+            assert abs(abs(nacs[(m, n)][c]) - abs(ref)) < G_TOL
+            assert abs(nacs[(m, n)][c] + nacs[(n, m)][c]) < G_TOL
+
+
+def test_call_order_and_input_errors():
+    from paper_2403_01007_amd import Context
+    from paper_2403_01007_amd.binding import SccError
+    S = make_system("o2v4")
+    print("[errors]", flush=True)
+    h, L = S.at(np.zeros(S.ncoord))
+    ctx = Context(S.o, S.v, S.nj, S.nstates)
+    with pytest.raises(SccError) as e:
+        ctx.excited()
+    assert e.value.code == -2  # SCC_ESTATE: no Hamiltonian yet
+    # a non-Hartree-Fock basis (rotated orbitals) is rejected
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(S.o + S.v, S.o + S.v)) * 0.05
+    U = np.linalg.qr(np.eye(S.o + S.v) + X - X.T)[0]
+    with pytest.raises(SccError) as e:
+        ctx.set_hamiltonian(U.T @ h @ U, np.einsum("pr,Jrs,sq->Jpq", U.T, L, U))
+    assert e.value.code == -1  # SCC_EINVAL
+    ctx.set_hamiltonian(h, L)
+    with pytest.raises(SccError) as e:
+        ctx.gradient(0, S.dh, S.dL)
+    assert e.value.code == -2  # gradient before the excited states
+    ctx.excited()
+    with pytest.raises(SccError) as e:
+        ctx.gradient(S.nstates, S.dh, S.dL)
+    assert e.value.code == -1
+
+
+def test_deterministic():
+    """Two runs on the same inputs give bitwise identical results."""
+    S = make_system("o2v4")
+    print("[determinism]", flush=True)
+    a = _run_gpu(S)
+    b = _run_gpu(S)
+    assert a[1] == b[1]
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+    for k in a[4]:
+        assert np.array_equal(a[4][k], b[4][k])
+    for k in a[5]:
+        assert np.array_equal(a[5][k], b[5][k])
