@@ -24,8 +24,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="o10v90")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="fp32: FP32 products in the dense contractions, then FP64 refinement")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="with --precision fp32: also solve one geometry in FP64 (untimed) and report the "
+                         "largest differences and the FP64 time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
@@ -41,7 +46,8 @@ def main():
     S = make_system(args.workload)
     h, L = S.at(np.zeros(S.ncoord))
     dev = torch.device("cuda:0")
-    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11, verbose=args.verbose)
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11, verbose=args.verbose,
+                  precision=args.precision)
     h_d = torch.as_tensor(h, device=dev)
     L_d = torch.as_tensor(L, device=dev)
     dh = torch.as_tensor(S.dh, device=dev)
@@ -54,7 +60,7 @@ def main():
             print(f"[phase {name}: {info.seconds:.2f} s, {info.iterations} iterations, "
                   f"{info.flops_mfma / 1e12:.2f} TFLOP]", file=sys.stderr, flush=True)
 
-    def step():
+    def step(ctx=ctx):
         ctx.set_hamiltonian(h_d, L_d)
         E, zeta, info = ctx.excited()
         phase("excited", info)
@@ -69,6 +75,19 @@ def main():
             out[f"d{m}{n}"] = d
         return out
 
+    reference = None
+    if args.precision == "fp32" and args.compare_fp64:
+        ref_ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11, verbose=args.verbose)
+        r0 = time.perf_counter()
+        reference = step(ref_ctx)
+        torch.cuda.synchronize()
+        reference["seconds"] = time.perf_counter() - r0
+        ref_ctx.close()
+        del ref_ctx
+        print(f"[fp64 reference geometry done: {reference['seconds']:.1f} s]", file=sys.stderr, flush=True)
+    # load the kernels and touch every code path once outside the timed region
+    ctx.set_hamiltonian(h_d, L_d)
+    ctx.eval_residual(np.zeros(S.o * S.v * (1 + S.o * S.v)))
     for _ in range(args.warmup):
         step()
         print(f"[warmup step done]", file=sys.stderr, flush=True)
@@ -123,9 +142,9 @@ def main():
         "metric": "s/geometry (energies+gradients+NACs), MFMA TFLOP/s; mixed+learned vs FP64",
         "value": s_per_geom, "unit": "s/geometry", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * s_per_geom, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if args.precision == "fp64" else "f32-products+f64", "data": "synthetic",
         "config": {"workload": args.workload, "o": S.o, "v": S.v, "nchol": S.nj, "nstates": S.nstates,
-                   "ncoord": S.ncoord, "nacs": len(S.nacs), "precision": "fp64", "guess": "mp2/unit",
+                   "ncoord": S.ncoord, "nacs": len(S.nacs), "precision": args.precision, "guess": "mp2/unit",
                    "generator": S.reading},
         "tflops_contractions": (flops[0] / args.steps) / s_per_geom / 1e12,
         "roofline": {"bound": "mfma", "kernel": "gemm_f64_kernel", "achieved": achieved,
@@ -134,6 +153,13 @@ def main():
         "cpu_baseline": cpu,
         "energies": [float(x) for x in res["E"]],
     }
+    if reference is not None:
+        def maxdiff(prefix):
+            keys = [k for k in res if k.startswith(prefix)]
+            return max(float(np.abs(np.asarray(res[k]) - np.asarray(reference[k])).max()) for k in keys)
+        line["vs_fp64"] = {"fp64_seconds": reference["seconds"], "speedup": reference["seconds"] / s_per_geom,
+                           "max_abs_diff_energy": float(np.abs(res["E"] - reference["E"]).max()),
+                           "max_abs_diff_gradient": maxdiff("g"), "max_abs_diff_coupling": maxdiff("d")}
     print(json.dumps(line), flush=True)
 
 

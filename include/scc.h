@@ -67,6 +67,14 @@ typedef struct scc_options {
   int max_iter;          /* iteration limit of each solver */
   int scc;               /* 1: SCCSD(E); 0: plain CCSD / EOM-CCSD */
   int verbose;           /* 1: per-iteration log on stderr */
+  int precision;         /* 0: FP64 throughout.  1: the dense contractions
+                            (every GEMM with M, N, K >= 64: ladder, ring,
+                            hole-hole, Fock-dressed) take FP32 products with
+                            FP32 accumulation on the matrix cores until each
+                            solver reaches max(tol_residual, 1e-6); the
+                            solve is then refined in FP64 from that point.
+                            Residual norms, DIIS, subspace eigenproblems and
+                            orthogonalisation stay in FP64 in both modes. */
 } scc_options;
 
 typedef struct scc_info {
@@ -103,6 +111,24 @@ const char* scc_last_error(const scc_ctx* ctx);
  * SCC_EINVAL if max |F_ai| > 1e-6 (not a Hartree-Fock basis). */
 int scc_set_hamiltonian(scc_ctx* ctx, const double* h, const double* chol, double e_nuc);
 
+/* Hamiltonian of the current geometry in a fixed orthonormal basis (for
+ * example the orbitals of a reference geometry): h [N][N], chol [N_J][N][N]
+ * as in scc_set_hamiltonian but in that basis.  Solves the closed-shell RHF
+ * equations on the device (Fock builds from the Cholesky vectors, Roothaan
+ * iterations until max |F D - D F| < min(1e-12, 1e-2 tol_residual)),
+ * transforms the integrals to the canonical MO basis (Theory, orbitals of
+ * the current geometry; eq. H-bar-with-kappa at kappa = 0) and then acts as
+ * scc_set_hamiltonian.  orbitals_guess: NULL (start from the basis itself)
+ * or [N][N] starting orbitals (columns), e.g. those of the previous
+ * geometry; each converged orbital is signed to overlap its starting
+ * orbital positively.  orbitals: NULL or [N][N] converged orbitals out.
+ * After this call, scc_gradient / scc_nac take their derivative integrals
+ * in the same fixed basis and scc_densities returns densities in it.
+ * info (host, may be NULL): RHF iterations and final commutator norm.
+ * Returns SCC_ENOCONV if the RHF iterations do not converge in 500 steps. */
+int scc_set_hamiltonian_fixed_basis(scc_ctx* ctx, const double* h, const double* chol, double e_nuc,
+                                    const double* orbitals_guess, double* orbitals, scc_info* info);
+
 /* Ground state Omega(t) = 0 of CCSD (zeta = 0) (coupled cluster section,
  * eq. for Omega_mu).  guess_t: NULL or [t1 | t2]; e0: device double[1]. */
 int scc_ground(scc_ctx* ctx, const double* guess_t, double* e0, scc_info* info);
@@ -124,7 +150,8 @@ int scc_excited(scc_ctx* ctx, int nstates, const double* guess, double* energies
 int scc_multipliers(scc_ctx* ctx, int kind, int m, int n, scc_info* info);
 
 /* Effective densities of the last multiplier solve: d1 [N][N] = dL/dh,
- * z3 [N_J][N][N] = dL/dL^J (MO basis), kappa_bar [v][o].  Any may be NULL. */
+ * z3 [N_J][N][N] = dL/dL^J (MO basis, or the fixed basis after
+ * scc_set_hamiltonian_fixed_basis), kappa_bar [v][o].  Any may be NULL. */
 int scc_densities(scc_ctx* ctx, double* d1, double* z3, double* kappa_bar);
 
 /* Gradient g_n (eq. gradient_expression) along ncoord coordinates whose
@@ -163,7 +190,9 @@ int scc_profile(scc_ctx* ctx, int enable, double* gemm_ms, double* gemm_flops, l
  *   right transformation of vec [R0|R1|R2] at the current amplitudes
  *     -> out [sigma0 | sigma1 | sigma2]
  *   left transformation of vec -> out (same layout; doubles part symmetrised,
- *   i.e. the transformation restricted to (ai)<->(bj) symmetric vectors). */
+ *   i.e. the transformation restricted to (ai)<->(bj) symmetric vectors).
+ * With precision = 1 the residual hook evaluates with FP32 products in the
+ * dense contractions (the reduced-precision pass of the solvers). */
 int scc_eval_residual(scc_ctx* ctx, const double* t, const double* zeta, const double* xs, double* out);
 int scc_eval_sigma(scc_ctx* ctx, const double* vec, double* out);
 int scc_eval_left(scc_ctx* ctx, const double* vec, double* out);

@@ -13,7 +13,7 @@ ERRORS = {0: "SCC_OK", -1: "SCC_EINVAL", -2: "SCC_ESTATE", -3: "SCC_ENOCONV", -4
 FIELD_T, FIELD_R, FIELD_L, FIELD_E0, FIELD_OMEGA = 0, 1, 2, 3, 4
 
 EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_last_error",
-                    "scc_set_hamiltonian", "scc_ground", "scc_excited", "scc_multipliers",
+                    "scc_set_hamiltonian", "scc_set_hamiltonian_fixed_basis", "scc_ground", "scc_excited", "scc_multipliers",
                     "scc_densities", "scc_gradient", "scc_nac", "scc_get", "scc_eval_residual",
                     "scc_eval_sigma", "scc_eval_left", "scc_profile"]
 
@@ -25,7 +25,8 @@ class Dims(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("tol_residual", ctypes.c_double), ("tol_overlap", ctypes.c_double),
-                ("max_iter", ctypes.c_int), ("scc", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("scc", ctypes.c_int), ("verbose", ctypes.c_int),
+                ("precision", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -60,6 +61,7 @@ def load_library():
     lib.scc_last_error.argtypes = [P]
     lib.scc_last_error.restype = ctypes.c_char_p
     lib.scc_set_hamiltonian.argtypes = [P, P, P, D]
+    lib.scc_set_hamiltonian_fixed_basis.argtypes = [P, P, P, D, P, P, ctypes.POINTER(Info)]
     lib.scc_ground.argtypes = [P, P, P, ctypes.POINTER(Info)]
     lib.scc_excited.argtypes = [P, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_multipliers.argtypes = [P, I, I, I, ctypes.POINTER(Info)]
@@ -97,7 +99,7 @@ class Context:
     """Owns a libscc context plus its workspace (a torch uint8 CUDA tensor)."""
 
     def __init__(self, o, v, nj, nstates, tol=1e-10, tol_overlap=1e-11, max_iter=200, scc=True,
-                 verbose=False, device="cuda:0", stream=None):
+                 verbose=False, device="cuda:0", stream=None, precision="fp64"):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -105,7 +107,10 @@ class Context:
         self.n = o + v
         self.nov = o * v
         self.device = torch.device(device)
-        self.opts = Options(tol, tol_overlap, max_iter, 1 if scc else 0, 1 if verbose else 0)
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("precision must be 'fp64' or 'fp32'")
+        self.opts = Options(tol, tol_overlap, max_iter, 1 if scc else 0, 1 if verbose else 0,
+                            1 if precision == "fp32" else 0)
         self.dims = Dims(o, v, nj, nstates)
         nbytes = ctypes.c_size_t(0)
         self._check(self.lib.scc_workspace_bytes(ctypes.byref(self.dims), ctypes.byref(self.opts),
@@ -151,6 +156,18 @@ class Context:
         self._L = self._dev(chol)
         self._check(self.lib.scc_set_hamiltonian(self.h, _ptr(self._h), _ptr(self._L), float(e_nuc)),
                     "scc_set_hamiltonian")
+
+    def set_hamiltonian_fixed_basis(self, h, chol, e_nuc=0.0, orbitals_guess=None):
+        """RHF on the device, then as set_hamiltonian; returns the orbitals."""
+        self._h = self._dev(h)
+        self._L = self._dev(chol)
+        g = None if orbitals_guess is None else self._dev(orbitals_guess)
+        C = self.zeros(self.n, self.n)
+        info = Info()
+        self._check(self.lib.scc_set_hamiltonian_fixed_basis(self.h, _ptr(self._h), _ptr(self._L), float(e_nuc),
+                                                             _ptr(g), _ptr(C), ctypes.byref(info)),
+                    "scc_set_hamiltonian_fixed_basis")
+        return C, info
 
     def ground(self, guess=None):
         e0 = self.zeros(1)

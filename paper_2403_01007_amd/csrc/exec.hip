@@ -122,6 +122,100 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs a) {
       }
 }
 
+// Reduced-precision variant: FP64 operands are rounded to FP32 as they are
+// staged into LDS, multiplied on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32) with FP32 accumulation, and the result is written
+// back in FP64.  Same tiling and operand mapping as gemm_f64_kernel.
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_kernel(GemmArgs a) {
+  __shared__ float As[BK][BM + 1];
+  __shared__ float Bs[BK][BN + 1];
+  const int64_t split = a.splits > 1 ? blockIdx.z : 0;
+  const int64_t bz = a.splits > 1 ? 0 : blockIdx.z;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const double* A = a.A + bz * a.sAb;
+  const double* B = a.B + bz * a.sBb;
+  const int64_t kbeg = a.splits > 1 ? split * a.kchunk : 0;
+  const int64_t kend = a.splits > 1 ? min(a.K, kbeg + a.kchunk) : a.K;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 32;
+  const int wn = (wave & 1) * 32;
+  const bool a_kfast = (a.sAk == 1);
+  const bool b_nfast = (a.sBn == 1) || (a.sBk != 1);
+  f4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int e = 0; e < (BM * BK) / GEMM_THREADS; ++e) {
+      const int idx = tid + e * GEMM_THREADS;
+      int mm, kk;
+      if (a_kfast) {
+        kk = idx % BK;
+        mm = idx / BK;
+      } else {
+        mm = idx % BM;
+        kk = idx / BM;
+      }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      As[kk][mm] = (gm < a.M && gk < kend) ? (float)A[gm * a.sAm + gk * a.sAk] : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < (BN * BK) / GEMM_THREADS; ++e) {
+      const int idx = tid + e * GEMM_THREADS;
+      int nn, kk;
+      if (b_nfast) {
+        nn = idx % BN;
+        kk = idx / BN;
+      } else {
+        kk = idx % BK;
+        nn = idx / BK;
+      }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      Bs[kk][nn] = (gn < a.N && gk < kend) ? (float)B[gk * a.sBk + gn * a.sBn] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      float af[2], bf[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        af[t] = As[kr][wm + t * 16 + (lane & 15)];
+        bf[t] = Bs[kr][wn + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // v_mfma_f32_16x16x4_f32: lane l, register r holds D[4 (l / 16) + r][l % 16]
+  double* out = a.splits > 1 ? a.P + split * a.M * a.N : a.C + bz * a.sCb;
+  const double* Cin = (a.splits > 1 || !a.Cin) ? nullptr : a.Cin + bz * a.sCb;
+  const int64_t sm = a.splits > 1 ? a.N : a.sCm, sn = a.splits > 1 ? 1 : a.sCn;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const int64_t col = n0 + wn + j * 16 + (lane & 15);
+        if (row < a.M && col < a.N) {
+          double v = a.alpha * (double)acc[i][j][r];
+          if (Cin) v += a.beta * Cin[row * a.sCm + col * a.sCn];
+          out[row * sm + col * sn] = v;
+        }
+      }
+}
+
 __global__ void splitk_reduce_kernel(GemmArgs a) {
   const int64_t mn = a.M * a.N;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -248,13 +342,16 @@ static unsigned grid_for(int64_t n, int threads = 256) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
 }
 
-void launch_gemm_main(const GemmArgs& a, hipStream_t s) {
+void launch_gemm_main(const GemmArgs& a, hipStream_t s, bool f32) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return;
   if (a.splits > 1 && (a.batch != 1 || !a.P || a.kchunk <= 0)) throw std::runtime_error("bad split-K plan");
   dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((a.M + BM - 1) / BM),
             (unsigned)(a.splits > 1 ? a.splits : a.batch));
   if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm grid too large");
-  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(GEMM_THREADS), 0, s, a);
+  if (f32)
+    hipLaunchKernelGGL(gemm_f32acc_kernel, grid, dim3(GEMM_THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(GEMM_THREADS), 0, s, a);
   check(hipGetLastError(), "gemm launch");
 }
 
@@ -277,6 +374,98 @@ __global__ void combine_kernel(const double* __restrict__ X, int k, int64_t n, c
     for (int j = 0; j < k; ++j) acc += coef[j] * X[(int64_t)j * n + i];
     y[i] = acc;
   }
+}
+
+__global__ __launch_bounds__(256) void gemv_rows_kernel(GemvArgs g) {
+  // one wave per row; lanes stride over the unit-stride k index
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  if (row >= g.R) return;  // the whole wave leaves together (no barriers below)
+  const int64_t split = blockIdx.y;
+  const int64_t kb = split * g.kchunk;
+  const int64_t ke = g.splits > 1 ? min(g.K, kb + g.kchunk) : g.K;
+  const double* m = g.Mt + row * g.sr;
+  double acc = 0.0;
+  for (int64_t k = kb + lane; k < ke; k += 64) acc += m[k * g.sk] * g.x[k * g.sx];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    if (g.splits > 1) {
+      g.P[split * g.R + row] = acc;
+    } else {
+      double v = g.alpha * acc;
+      if (g.yin) v += g.beta * g.yin[row * g.sy];
+      g.y[row * g.sy] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void gemv_cols_kernel(GemvArgs g) {
+  // one thread per row; neighbouring threads read neighbouring rows
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= g.R) return;
+  const int64_t split = blockIdx.y;
+  const int64_t kb = split * g.kchunk;
+  const int64_t ke = g.splits > 1 ? min(g.K, kb + g.kchunk) : g.K;
+  const double* m = g.Mt + row * g.sr;
+  double acc = 0.0;
+  for (int64_t k = kb; k < ke; ++k) acc += m[k * g.sk] * g.x[k * g.sx];
+  if (g.splits > 1) {
+    g.P[split * g.R + row] = acc;
+  } else {
+    double v = g.alpha * acc;
+    if (g.yin) v += g.beta * g.yin[row * g.sy];
+    g.y[row * g.sy] = v;
+  }
+}
+
+__global__ void gemv_reduce_kernel(GemvArgs g) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < g.R; r += stride) {
+    double v = 0.0;
+    for (int64_t s = 0; s < g.splits; ++s) v += g.P[s * g.R + r];
+    v *= g.alpha;
+    if (g.yin) v += g.beta * g.yin[r * g.sy];
+    g.y[r * g.sy] = v;
+  }
+}
+
+void launch_gemv(const GemvArgs& g, hipStream_t s) {
+  if (g.R <= 0) return;
+  if (g.splits > 1 && (!g.P || g.kchunk <= 0)) throw std::runtime_error("bad split GEMV plan");
+  const int64_t bx = g.rows ? (g.R + 3) / 4 : (g.R + 255) / 256;
+  if (bx > 0x7fffffff || g.splits > 65535) throw std::runtime_error("GEMV grid too large");
+  dim3 grid((unsigned)bx, (unsigned)g.splits);
+  if (g.rows)
+    hipLaunchKernelGGL(gemv_rows_kernel, grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(gemv_cols_kernel, grid, dim3(256), 0, s, g);
+  check(hipGetLastError(), "gemv launch");
+  if (g.splits > 1) {
+    hipLaunchKernelGGL(gemv_reduce_kernel, dim3(grid_for(g.R)), dim3(256), 0, s, g);
+    check(hipGetLastError(), "gemv reduce launch");
+  }
+}
+
+__global__ void outer_kernel(GemmArgs a, int nfast) {
+  const int64_t mn = a.M * a.N, total = mn * a.batch;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < total; lin += stride) {
+    const int64_t b = lin / mn, r = lin % mn;
+    const int64_t m = nfast ? r / a.N : r % a.M;
+    const int64_t n = nfast ? r % a.N : r / a.M;
+    double v = a.alpha * a.A[b * a.sAb + m * a.sAm] * a.B[b * a.sBb + n * a.sBn];
+    const int64_t o = b * a.sCb + m * a.sCm + n * a.sCn;
+    if (a.Cin) v += a.beta * a.Cin[o];
+    a.C[o] = v;
+  }
+}
+
+void launch_outer(const GemmArgs& a, hipStream_t s) {
+  const int64_t total = a.M * a.N * a.batch;
+  if (total <= 0) return;
+  const int nfast = (a.sCn == 1 || a.sCm != 1) ? 1 : 0;
+  hipLaunchKernelGGL(outer_kernel, dim3(grid_for(total)), dim3(256), 0, s, a, nfast);
+  check(hipGetLastError(), "outer launch");
 }
 
 void launch_combine(const double* X, int k, int64_t n, const double* coef, double* y, hipStream_t s) {
@@ -564,13 +753,60 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
       p.total = total;
     }
   }
+  // degenerate shapes are memory-bound: no matrix cores
+  if (K == 1) {
+    P.kind = ContractKind::Outer;
+    P.scratch = sc;
+    return P;
+  }
+  if (Bt == 1 && (N == 1 || M == 1)) {
+    GemvArgs& v = P.gv;
+    v = GemvArgs{};
+    v.K = K;
+    v.alpha = G.alpha;
+    v.beta = G.beta;
+    v.y = G.C;
+    v.yin = G.Cin;
+    if (N == 1) {
+      v.R = M;
+      v.Mt = G.A;
+      v.sr = G.sAm;
+      v.sk = G.sAk;
+      v.x = G.B;
+      v.sx = G.sBk;
+      v.sy = G.sCm;
+    } else {
+      v.R = N;
+      v.Mt = G.B;
+      v.sr = G.sBn;
+      v.sk = G.sBk;
+      v.x = G.A;
+      v.sx = G.sAk;
+      v.sy = G.sCn;
+    }
+    v.rows = v.sk == 1 && v.sr != 1;
+    const int64_t blocks = v.rows ? (v.R + 3) / 4 : (v.R + 255) / 256;
+    const int64_t kmin = v.rows ? 512 : 64;
+    int64_t sp = std::min<int64_t>((1024 + blocks - 1) / blocks, K / kmin);
+    sp = std::min<int64_t>(sp, 4096);
+    if (sp > 1) {
+      const int64_t kc = (K + sp - 1) / sp;
+      v.splits = (K + kc - 1) / kc;
+      v.kchunk = kc;
+      v.P = scratch + sc;
+      sc += v.splits * v.R;
+    }
+    P.kind = ContractKind::Gemv;
+    P.scratch = sc;
+    return P;
+  }
   // split-K when the output tiles cannot fill the chip and K is long
   {
     const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * Bt;
     const int64_t target = 1024;
-    if (Bt == 1 && K >= 512 && tiles < target) {
-      int64_t sp = std::min<int64_t>((target + tiles - 1) / tiles, K / 256);
-      sp = std::min<int64_t>(sp, 64);
+    if (Bt == 1 && K >= 128 && tiles < target) {
+      int64_t sp = std::min<int64_t>((target + tiles - 1) / tiles, K / 64);
+      sp = std::min<int64_t>(sp, 1024);
       if (sp > 1) {
         int64_t kc = (K + sp - 1) / sp;
         kc = (kc + BK - 1) / BK * BK;
@@ -617,6 +853,7 @@ void Executor::set_profile(bool on) {
     for (auto& e : ev_) check(hipEventCreate(&e), "event create");
     ev_flops_.resize(4096);
     ev_shape_.resize(4096);
+    ev_f32_.resize(4096);
   }
   if (!on) flush_profile();
   prof_ = on;
@@ -628,22 +865,29 @@ void Executor::flush_profile() {
   for (size_t i = 0; i < nev_; ++i) {
     float ms = 0;
     check(hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]), "event elapsed");
+    if (ev_f32_[i]) {
+      f32_ms += ms;
+      f32_flops += ev_flops_[i];
+      ++f32_launches;
+      continue;
+    }
     gemm_ms += ms;
     gemm_flops += ev_flops_[i];
+    ++gemm_launches;
     ShapeStat& st = shapes_[ev_shape_[i]];
     st.n += 1;
     st.ms += ms;
     st.flops += ev_flops_[i];
   }
-  gemm_launches += (int64_t)nev_;
   nev_ = 0;
 }
 
-void Executor::timed_gemm(const GemmArgs& g, hipStream_t s) {
+void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32) {
   if (nev_ == ev_flops_.size()) flush_profile();
   // the events bracket the MFMA kernel alone (a split-K reduction follows)
   check(hipEventRecord(ev_[2 * nev_], s), "event record");
-  launch_gemm_main(g, s);
+  launch_gemm_main(g, s, f32);
+  ev_f32_[nev_] = f32 ? 1 : 0;
   check(hipEventRecord(ev_[2 * nev_ + 1], s), "event record");
   launch_gemm_reduce(g, s);
   ev_flops_[nev_] = 2.0 * g.M * g.N * g.K * g.batch;
@@ -691,11 +935,20 @@ void Executor::run_op(int k, hipStream_t s) {
       if (p.packB) launch_perm(p.pb, s);
       if (p.dot) {
         launch_dot(p.g.A, p.g.B, p.g.K, p.g.alpha, p.g.Cin, p.g.beta, p.g.C, partials_, s);
+      } else if (p.kind == ContractKind::Outer) {
+        launch_outer(p.g, s);
+        if (p.tmpC) launch_perm(p.pc, s);
+      } else if (p.kind == ContractKind::Gemv) {
+        launch_gemv(p.gv, s);
+        if (p.tmpC) launch_perm(p.pc, s);
       } else {
-        if (prof_)
-          timed_gemm(p.g, s);
-        else
-          launch_gemm(p.g, s);
+        const bool f32 = lowp_ && p.g.M >= 64 && p.g.N >= 64 && p.g.K >= 64;
+        if (prof_) {
+          timed_gemm(p.g, s, f32);
+        } else {
+          launch_gemm_main(p.g, s, f32);
+          launch_gemm_reduce(p.g, s);
+        }
         if (p.tmpC) launch_perm(p.pc, s);
       }
       break;

@@ -49,7 +49,7 @@ struct PermArgs {
 
 void launch_gemm(const GemmArgs& a, hipStream_t s);
 // the MFMA kernel alone, and the split-K reduction that follows it
-void launch_gemm_main(const GemmArgs& a, hipStream_t s);
+void launch_gemm_main(const GemmArgs& a, hipStream_t s, bool f32 = false);
 void launch_gemm_reduce(const GemmArgs& a, hipStream_t s);
 // y[i] += sum_j coef[j] X[j][i] over X [k][n] (coef: device, k entries)
 void launch_combine(const double* X, int k, int64_t n, const double* coef, double* y, hipStream_t s);
@@ -70,9 +70,35 @@ void launch_sym_pairs(double* x, int64_t nov, hipStream_t s);
 void launch_deriv_contract(const double* dh, int64_t nh, const double* D1, const double* dL, int64_t nl,
                            const double* Z, int ncoord, double* grad, double* partials, hipStream_t s);
 
+// y[r] = alpha * sum_k Mt[r sr + k sk] x[k sx] + beta * yin[r sy]: a
+// contraction with one free index (GEMV).  splits > 1 writes partial sums
+// over K chunks into P[split][r]; a second pass adds them in a fixed order.
+struct GemvArgs {
+  int64_t R, K;
+  const double* Mt;
+  int64_t sr, sk;
+  const double* x;
+  int64_t sx;
+  double alpha, beta;
+  const double* yin;
+  double* y;
+  int64_t sy;
+  int64_t splits = 1, kchunk = 0;
+  double* P = nullptr;
+  bool rows = false;  // k is the matrix's unit-stride index: one wave per row
+};
+
+void launch_gemv(const GemvArgs& g, hipStream_t s);
+// K == 1: C[b][m][n] = alpha A[b][m] B[b][n] + beta Cin[b][m][n]
+void launch_outer(const GemmArgs& g, hipStream_t s);
+
+enum class ContractKind { Mfma, Dot, Gemv, Outer };
+
 struct ContractPlan {
   // operand packs: -1 = use directly
   bool packA = false, packB = false, tmpC = false, dot = false;
+  ContractKind kind = ContractKind::Mfma;
+  GemvArgs gv{};
   GemmArgs g{};
   PermArgs pa{}, pb{}, pc{};
   int64_t scratch = 0;  // doubles of scratch needed
@@ -91,8 +117,14 @@ class Executor {
   // GEMM kernel timing with HIP events (off by default)
   void set_profile(bool on);
   void flush_profile();
+  // FP64 kernel totals; FP32-product kernel totals (reduced-precision mode)
   double gemm_ms = 0.0, gemm_flops = 0.0;
   int64_t gemm_launches = 0;
+  double f32_ms = 0.0, f32_flops = 0.0;
+  int64_t f32_launches = 0;
+  // reduced precision: dense contractions (M, N, K >= 64) take FP32 products
+  void set_lowp(bool on) { lowp_ = on; }
+  bool lowp() const { return lowp_; }
   // per-shape totals of the timed launches, largest time first
   void shape_report(FILE* f, int top) const;
   ~Executor();
@@ -104,7 +136,8 @@ class Executor {
   int64_t scratch_n_;
   double* partials_;
   std::vector<ContractPlan> plans_;
-  bool prof_ = false;
+  bool prof_ = false, lowp_ = false;
+  std::vector<char> ev_f32_;
   std::vector<hipEvent_t> ev_;
   std::vector<double> ev_flops_;
   std::vector<std::array<int64_t, 5>> ev_shape_;
@@ -115,7 +148,7 @@ class Executor {
   std::map<std::array<int64_t, 5>, ShapeStat> shapes_;
   size_t nev_ = 0;
   void run_op(int k, hipStream_t s);
-  void timed_gemm(const GemmArgs& g, hipStream_t s);
+  void timed_gemm(const GemmArgs& g, hipStream_t s, bool f32);
 };
 
 ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* scratch);

@@ -415,7 +415,8 @@ static std::vector<int> op_inputs(const Op& op) {
   return r;
 }
 
-int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, int64_t align) {
+int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, const std::vector<int>& pinned,
+                        int64_t align) {
   auto rnd = [&](int64_t n) { return (n + align - 1) / align * align; };
   const int nt = (int)t.size();
   // owner program of each tensor's producer and of each consumer (-2: several)
@@ -444,6 +445,8 @@ int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, in
       for (int in : op_inputs(ops[k]))
         if (dead[in]) throw std::runtime_error("a program reads a tensor no program computes");
   for (int i = 0; i < nt; ++i) temp[i] = !t[i].zero && prod_prog[i] >= 0 && use_prog[i] == prod_prog[i];
+  for (int i : pinned)
+    if (i >= 0 && i < nt) temp[i] = 0;
   // persistent storage
   int64_t pos = 0;
   for (int i = 0; i < nt; ++i) {

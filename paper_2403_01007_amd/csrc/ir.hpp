@@ -111,7 +111,10 @@ class Graph {
   // (and read nowhere else) are temporaries: they share one region, reused
   // within each program by liveness (programs run one at a time).  All
   // other tensors get storage of their own.
-  int64_t finalize(const std::vector<const std::vector<int>*>& programs, int64_t align = 32);
+  // Tensors in `pinned` (read or written by host code) always get storage of
+  // their own.
+  int64_t finalize(const std::vector<const std::vector<int>*>& programs, const std::vector<int>& pinned,
+                   int64_t align = 32);
 
  private:
   void check_labels(const std::string& l, int id, const char* what) const;

@@ -421,6 +421,31 @@ void build_model(Model& m, const Dims& d, int nb) {
       for (int k : minus(*pr, g.dependent_ops(*pr, mult_in))) pre.insert(k);
     m.p_lag_pre.assign(pre.begin(), pre.end());
   }
+  // fixed-basis Hamiltonian: Fock matrix of the closed-shell determinant
+  // of orbitals Cmo, F = h + sum_J [2 L^J tr(L^J D) - L^J D L^J] with
+  // D = C_occ C_occ^T; MO integrals C^T h C, C^T L^J C; densities back to
+  // the fixed basis, C D1 C^T and C Z^J C^T
+  {
+    m.hao = g.tensor({n, n}, "h_fixed");
+    m.Lao = g.tensor({J, n, n}, "L_fixed");
+    m.Cmo = g.tensor({n, n}, "C");
+    int b0 = (int)g.ops.size();
+    int Cocc = g.slice(m.Cmo, {0, 0}, {n, o});
+    int Dao = g.contract("pi,qi->pq", Cocc, Cocc);
+    int dJ = g.contract("Jpq,pq->J", m.Lao, Dao);
+    int X = g.contract("Jpr,rs->Jps", m.Lao, Dao);
+    m.Fao = g.contract("Jps,Jsq->pq", X, m.Lao, -1.0, g.contract("Jpq,J->pq", m.Lao, dJ, 2.0, m.hao));
+    int b1 = (int)g.ops.size();
+    m.hmo = g.contract("pP,pQ->PQ", m.Cmo, g.contract("pq,qQ->pQ", m.hao, m.Cmo));
+    m.Lmo = g.contract("pP,JpQ->JPQ", m.Cmo, g.contract("Jpq,qQ->JpQ", m.Lao, m.Cmo));
+    int b2 = (int)g.ops.size();
+    m.d1ao = g.contract("pP,Pq->pq", m.Cmo, g.contract("PQ,qQ->Pq", m.a_h, m.Cmo));
+    m.zao = g.contract("pP,JPq->Jpq", m.Cmo, g.contract("JPQ,qQ->JPq", m.a_L, m.Cmo));
+    int b3 = (int)g.ops.size();
+    for (int k = b0; k < b1; ++k) m.p_aofock.push_back(k);
+    for (int k = b1; k < b2; ++k) m.p_aotrans.push_back(k);
+    for (int k = b2; k < b3; ++k) m.p_aodens.push_back(k);
+  }
   // coupling targets O_mn for each ket state n
   m.nac_l = new_state(g, d, "nac_l");
   m.nac_t1c = g.tensor({v, o}, "nac_t1c");
@@ -444,10 +469,37 @@ void build_model(Model& m, const Dims& d, int nb) {
   }
 }
 
+std::vector<int> host_tensors(const Model& m) {
+  std::vector<int> r = {m.In,   m.Io,  m.one,     m.z2,      m.h,      m.L,      m.kappa,  m.hk,   m.Lk,
+                        m.G,    m.fock, m.t1,     m.t2,      m.res.E,  m.res.O1, m.res.O2, m.sig.s0, m.sig.s1,
+                        m.sig.s2, m.ovl, m.dens_hk, m.pt1, m.pt2,    m.fai,    m.m1,     m.m2,   m.mF,
+                        m.a_t1, m.a_t2, m.a_kappa, m.a_h,     m.a_L,    m.fk_adj, m.nac_t1c, m.nac_t2c,
+                        m.hao,  m.Lao,  m.Cmo,     m.Fao,     m.hmo,    m.Lmo,    m.d1ao,    m.zao};
+  auto st = [&](const StateT& s) {
+    r.push_back(s.r0);
+    r.push_back(s.r1);
+    r.push_back(s.r2);
+  };
+  auto sg = [&](const SigmaOut& s) {
+    r.push_back(s.s0);
+    r.push_back(s.s1);
+    r.push_back(s.s2);
+  };
+  for (auto* v : {&m.zeta, &m.pz, &m.pE, &m.mN, &m.mO, &m.a_z, &m.a_E, &m.onac, &m.a_nac_t1, &m.a_nac_t2})
+    r.insert(r.end(), v->begin(), v->end());
+  for (auto* v : {&m.xs, &m.pr, &m.lam, &m.a_r, &m.a_nac_r})
+    for (auto& s : *v) st(s);
+  for (auto& s : m.mk) sg(s);
+  for (const StateT* s : {&m.vin, &m.lin, &m.lout, &m.oa, &m.ob, &m.nac_l, &m.vinB, &m.sigB, &m.linB, &m.loutB})
+    st(*s);
+  return r;
+}
+
 std::vector<const std::vector<int>*> programs(const Model& m) {
   std::vector<const std::vector<int>*> r = {&m.p_setup, &m.p_res,      &m.p_sig_pre, &m.p_sig,   &m.p_left,
                                             &m.p_ovl,   &m.p_dens,     &m.p_lag_pre, &m.p_lag,   &m.p_kappa,
-                                            &m.p_fk,    &m.p_integral, &m.p_sigB,    &m.p_leftB};
+                                            &m.p_fk,    &m.p_integral, &m.p_sigB,    &m.p_leftB,
+                                            &m.p_aofock, &m.p_aotrans, &m.p_aodens};
   for (auto& p : m.p_nac) r.push_back(&p);
   return r;
 }

@@ -86,6 +86,13 @@ struct Model {
   std::vector<StateT> a_nac_r;          // per n
   std::vector<std::vector<int>> p_nac;  // per n
 
+  // --- Hamiltonian given in a fixed orthonormal basis: RHF Fock matrix for
+  //     orbitals Cmo (columns), the MO transformation, and the effective
+  //     densities transformed back to the fixed basis
+  int hao = -1, Lao = -1, Cmo = -1;
+  int Fao = -1, hmo = -1, Lmo = -1, d1ao = -1, zao = -1;
+  std::vector<int> p_aofock, p_aotrans, p_aodens;
+
   // --- right / left transformations of a block of nb vectors at once
   //     (leading batch index on every input, output and intermediate)
   int nb = 1;
@@ -101,5 +108,8 @@ void build_model(Model& m, const Dims& d, int nb = 1);
 
 // Every op list the context runs (the storage plan relies on this list).
 std::vector<const std::vector<int>*> programs(const Model& m);
+// Every tensor the host reads or writes between programs (never reused as a
+// program temporary).
+std::vector<int> host_tensors(const Model& m);
 
 }  // namespace scc

@@ -107,6 +107,8 @@ struct scc_ctx {
   std::vector<double> eps;
   bool have_h = false, have_ground = false, have_excited = false, have_mult = false;
   bool scc_on = false;        // the SCC constraint (zeta, O_kl) is part of the solution
+  std::vector<double> Jz;     // zeta Jacobian dO/dzeta of the last SCC solve
+  bool fixed_basis = false;   // Hamiltonian (and derivative integrals) in a fixed basis
   double E0 = 0.0, enuc = 0.0;
   std::vector<double> E, zeta;
   int mult_kind = -1, mult_m = -1, mult_n = -1;
@@ -615,25 +617,33 @@ std::vector<double> pair_overlaps(scc_ctx* c) {
   return O;
 }
 
-int excited_solve(scc_ctx* c, scc_info* info) {
+// One solve of the excited states.  warm: continue from the zeta, amplitudes,
+// vectors and zeta Jacobian of a previous pass (the FP64 refinement of a
+// reduced-precision solve); otherwise start from CCSD at zeta = 0.
+int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& iters) {
   const int ns = c->m.d.ns, np = c->m.d.npairs();
-  const double tol = c->opt.tol_residual;
   const int maxit = c->opt.max_iter;
-  int iters = 0;
-  c->zeta.assign(np, 0.0);
-  set_scc_inputs(c, c->zeta, false);
   const bool use_scc = c->opt.scc && c->m.d.o >= 2 && np > 0;
   c->scc_on = use_scc;
-  // with the constraint active, the CCSD states are only the starting point:
-  // left vectors are solved once, at the converged SCC point
-  int rc = excited_at_fixed_zeta(c, tol, maxit, false, iters, !use_scc);
-  if (rc) return rc;
+  int rc = SCC_OK;
+  if (!warm) {
+    c->zeta.assign(np, 0.0);
+    c->Jz.clear();
+    set_scc_inputs(c, c->zeta, false);
+    // with the constraint active, the CCSD states are only the starting
+    // point: left vectors are solved once, at the converged SCC point
+    rc = excited_at_fixed_zeta(c, tol, maxit, false, iters, !use_scc);
+    if (rc) return rc;
+  } else if (!use_scc) {
+    for (int k = 0; k < ns; ++k) c->cp(c->Lv[k], c->R[k], c->sz.nst);
+    return excited_at_fixed_zeta(c, tol, maxit, true, iters, true);
+  }
   if (use_scc) {
     const int64_t nst = c->sz.nst;
     int64_t mark = c->pool_used;
     std::vector<double*> prev(ns);
     for (int k = 0; k < ns; ++k) prev[k] = c->alloc(nst);
-    std::vector<double> Jz;
+    std::vector<double>& Jz = c->Jz;
     std::vector<double> z = c->zeta, Oprev, zprev;
     bool conv = false;
     double omax_prev = 1.0;
@@ -658,7 +668,7 @@ int excited_solve(scc_ctx* c, scc_info* info) {
       for (double x : O) omax = std::max(omax, std::fabs(x));
       c->log(" scc it %2d  max|O| %.3e  |dR| %.3e  zeta0 %.8f  (inner tol %.1e)\n", it, omax, dR, z[0], tol_it);
       omax_prev = omax;
-      if (omax < c->opt.tol_overlap && dR < 10 * tol && tol_it <= tol) {
+      if (omax < tol_overlap && dR < 10 * tol && tol_it <= tol) {
         conv = true;
         break;
       }
@@ -719,6 +729,25 @@ int excited_solve(scc_ctx* c, scc_info* info) {
     rc = excited_at_fixed_zeta(c, tol, maxit, true, iters, true);
     if (rc) return rc;
   }
+  return SCC_OK;
+}
+
+// reduced-precision mode: FP32-product pass to this tolerance, then FP64
+constexpr double LOWP_TOL = 1e-6;
+
+int excited_solve(scc_ctx* c, scc_info* info) {
+  const double tol = c->opt.tol_residual, tov = c->opt.tol_overlap;
+  int iters = 0, rc;
+  if (c->opt.precision == 1) {
+    c->ex->set_lowp(true);
+    rc = excited_pass(c, std::max(tol, LOWP_TOL), std::max(tov, LOWP_TOL), false, iters);
+    c->ex->set_lowp(false);
+    if (rc) return rc;
+    rc = excited_pass(c, tol, tov, true, iters);
+  } else {
+    rc = excited_pass(c, tol, tov, false, iters);
+  }
+  if (rc) return rc;
   if (info) {
     info->iterations = iters;
     info->converged = 1;
@@ -820,15 +849,22 @@ int gmres(scc_ctx* c, int64_t n, const LinOp& A, const LinOp& Minv, const double
 // the Lagrangian Jacobian).  Equivalent to unrestarted GMRES for one RHS.
 // ---------------------------------------------------------------------------
 int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const double* b, double* x, double tol,
-        int maxit, int& iters, double& relres) {
+        int maxit, int& iters, double& relres, bool warm = false) {
   const int64_t n = rc.n;
   int64_t mark = c->pool_used;
   double* r = c->alloc(n);
   double* z = c->alloc(n);
   double* w = c->alloc(n);
   double bn = std::sqrt(c->dot(b, b, n));
-  c->fill(x, n, 0.0);
-  c->cp(r, b, n);
+  if (warm) {
+    // continue from the given x: r = b - A x
+    A(x, w);
+    c->cp(r, b, n);
+    c->axpby(-1.0, w, 1.0, r, n);
+  } else {
+    c->fill(x, n, 0.0);
+    c->cp(r, b, n);
+  }
   iters = 0;
   relres = 1.0;
   if (bn == 0) {
@@ -1045,8 +1081,21 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   };
   int iters = 0;
   double rel = 0;
-  int rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, std::max(c->opt.max_iter, c->rec_lag.cap),
-               iters, rel);
+  const int maxg = std::max(c->opt.max_iter, c->rec_lag.cap);
+  int rc;
+  if (c->opt.precision == 1) {
+    // FP32-product pass, then FP64 refinement from its solution
+    c->ex->set_lowp(true);
+    rc = gcr(c, c->rec_lag, apply, prec, b, x, std::max(c->opt.tol_residual, LOWP_TOL), maxg, iters, rel);
+    c->ex->set_lowp(false);
+    if (rc == SCC_OK) {
+      int it2 = 0;
+      rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, it2, rel, true);
+      iters += it2;
+    }
+  } else {
+    rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, iters, rel);
+  }
   if (rc) {
     c->pool_used = mark;
     return rc;
@@ -1133,6 +1182,8 @@ int guarded(scc_ctx* c, scc_info* info, F&& f) {
     if (c) c->err = e.what();
     rc = SCC_EDEVICE;
   }
+  // every call leaves the executor in FP64 mode
+  if (c) c->ex->set_lowp(false);
   if (info) {
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->flops_mfma = c ? c->flops - f0 : 0;
@@ -1151,6 +1202,7 @@ void default_opts(const scc_options* o, scc_options& out) {
   out.max_iter = 200;
   out.scc = 1;
   out.verbose = 0;
+  out.precision = 0;
   if (o) out = *o;
   if (out.tol_residual <= 0) out.tol_residual = 1e-10;
   if (out.tol_overlap <= 0) out.tol_overlap = 1e-11;
@@ -1168,13 +1220,19 @@ Plan make_plan(const scc_dims* d) {
   p.m = std::make_unique<Model>();
   Dims dd{d->nocc, d->nvirt, d->nocc + d->nvirt, d->nchol, d->nstates};
   build_model(*p.m, dd, dd.ns + 2);
-  p.arena = up(p.m->g.finalize(programs(*p.m)), 32);
+  p.arena = up(p.m->g.finalize(programs(*p.m), host_tensors(*p.m)), 32);
   p.scratch = up(std::max<int64_t>(Executor::plan_scratch(p.m->g), 32));
   p.pool = up(sizes_for(dd).pool);
   p.bytes = (size_t)(p.arena + p.scratch + PARTIALS + p.pool) * sizeof(double) + 256;
   return p;
 }
 
+}  // namespace
+
+namespace {
+int install_mo_hamiltonian_impl(scc_ctx* c, double e_nuc);
+// MO-basis integrals are in m.h / m.L: derived quantities, checks, reset
+int install_mo_hamiltonian(scc_ctx* c, double e_nuc) { return install_mo_hamiltonian_impl(c, e_nuc); }
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1275,6 +1333,84 @@ int scc_set_hamiltonian(scc_ctx* c, const double* h, const double* chol, double 
     Model& m = c->m;
     c->cp(c->tp(m.h), h, m.g.t[m.h].size());
     c->cp(c->tp(m.L), chol, m.g.t[m.L].size());
+    c->fixed_basis = false;
+    return install_mo_hamiltonian(c, e_nuc);
+  });
+}
+
+int scc_set_hamiltonian_fixed_basis(scc_ctx* c, const double* h, const double* chol, double e_nuc,
+                                    const double* orbitals_guess, double* orbitals, scc_info* info) {
+  if (!c || !h || !chol) return SCC_EINVAL;
+  c->have_h = c->have_ground = c->have_excited = c->have_mult = false;
+  return guarded(c, info, [&]() -> int {
+    Model& m = c->m;
+    const int N = m.d.n, o = m.d.o;
+    c->cp(c->tp(m.hao), h, m.g.t[m.hao].size());
+    c->cp(c->tp(m.Lao), chol, m.g.t[m.Lao].size());
+    // reference orbitals: the guess (phase reference too) or the basis itself
+    std::vector<double> ref((size_t)N * N, 0.0), C, F((size_t)N * N), w, V;
+    if (orbitals_guess) {
+      c->sync();
+      hck(hipMemcpy(ref.data(), orbitals_guess, ref.size() * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      for (int p = 0; p < N; ++p) ref[(size_t)p * N + p] = 1.0;
+    }
+    C = ref;
+    // Roothaan iterations: F(C) diagonalised, occupied = lowest o orbitals,
+    // until the Fock matrix commutes with the density, max |F D - D F| < tol
+    const double tol = std::min(1e-12, 1e-2 * c->opt.tol_residual);
+    int it = 0;
+    double comm = 1.0;
+    for (; it < 500; ++it) {
+      hck(hipMemcpyAsync(c->tp(m.Cmo), C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+      c->run(m.p_aofock);
+      c->sync();
+      hck(hipMemcpy(F.data(), c->tp(m.Fao), F.size() * sizeof(double), hipMemcpyDeviceToHost));
+      std::vector<double> D((size_t)N * N, 0.0);
+      for (int p = 0; p < N; ++p)
+        for (int q = 0; q < N; ++q) {
+          double x = 0;
+          for (int i = 0; i < o; ++i) x += C[(size_t)p * N + i] * C[(size_t)q * N + i];
+          D[(size_t)p * N + q] = x;
+        }
+      comm = 0;
+      for (int p = 0; p < N; ++p)
+        for (int q = 0; q < N; ++q) {
+          double x = 0;
+          for (int r = 0; r < N; ++r) x += F[(size_t)p * N + r] * D[(size_t)r * N + q] - D[(size_t)p * N + r] * F[(size_t)r * N + q];
+          comm = std::max(comm, std::fabs(x));
+        }
+      if (comm < tol) break;
+      eig_sym(N, F, w, V);
+      // phase: each orbital overlaps its reference orbital positively
+      for (int k = 0; k < N; ++k) {
+        double sgn = 0;
+        for (int p = 0; p < N; ++p) sgn += ref[(size_t)p * N + k] * V[(size_t)p * N + k];
+        if (sgn < 0)
+          for (int p = 0; p < N; ++p) V[(size_t)p * N + k] = -V[(size_t)p * N + k];
+      }
+      C = V;
+    }
+    if (comm >= tol) throw SccError(SCC_ENOCONV, "RHF iterations did not converge");
+    c->log(" RHF converged in %d iterations (max |FD - DF| %.2e)\n", it, comm);
+    hck(hipMemcpyAsync(c->tp(m.Cmo), C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+    if (orbitals) hck(hipMemcpyAsync(orbitals, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+    c->run(m.p_aotrans);
+    c->cp(c->tp(m.h), c->tp(m.hmo), m.g.t[m.h].size());
+    c->cp(c->tp(m.L), c->tp(m.Lmo), m.g.t[m.L].size());
+    c->fixed_basis = true;
+    if (info) {
+      info->iterations = it;
+      info->residual = comm;
+      info->converged = 1;
+    }
+    return install_mo_hamiltonian(c, e_nuc);
+  });
+}
+
+namespace {
+int install_mo_hamiltonian_impl(scc_ctx* c, double e_nuc) {
+    Model& m = c->m;
     c->fill(c->tp(m.kappa), c->sz.nov, 0.0);
     c->run(m.p_setup);
     // orbital energies from the Fock diagonal
@@ -1330,8 +1466,8 @@ int scc_set_hamiltonian(scc_ctx* c, const double* h, const double* chol, double 
     c->rec_lag.reset();
     c->rec_k.reset();
     return SCC_OK;
-  });
 }
+}  // namespace
 
 int scc_ground(scc_ctx* c, const double* guess_t, double* e0, scc_info* info) {
   if (!c) return SCC_EINVAL;
@@ -1407,8 +1543,14 @@ int scc_densities(scc_ctx* c, double* d1, double* z3, double* kappa_bar) {
   if (!c->have_mult) return SCC_ESTATE;
   return guarded(c, nullptr, [&]() -> int {
     integral_adjoints(c);
-    if (d1) c->get(c->m.a_h, d1);
-    if (z3) c->get(c->m.a_L, z3);
+    if (c->fixed_basis) {
+      c->run(c->m.p_aodens);
+      if (d1) c->get(c->m.d1ao, d1);
+      if (z3) c->get(c->m.zao, z3);
+    } else {
+      if (d1) c->get(c->m.a_h, d1);
+      if (z3) c->get(c->m.a_L, z3);
+    }
     if (kappa_bar) c->cp(kappa_bar, c->kbar, c->sz.nov);
     return SCC_OK;
   });
@@ -1437,8 +1579,15 @@ static int derivative(scc_ctx* c, int kind, int mm, int nn, int ncoord, const do
     }
     integral_adjoints(c);
     const int64_t N = c->m.d.n, J = c->m.d.nj;
-    double* D1 = c->zero(c->m.a_h) ? nullptr : c->tp(c->m.a_h);
-    double* Z = c->zero(c->m.a_L) ? nullptr : c->tp(c->m.a_L);
+    int d1id = c->m.a_h, zid = c->m.a_L;
+    if (c->fixed_basis) {
+      // derivative integrals in the fixed basis: densities C D1 C^T, C Z C^T
+      c->run(c->m.p_aodens);
+      d1id = c->m.d1ao;
+      zid = c->m.zao;
+    }
+    double* D1 = c->zero(d1id) ? nullptr : c->tp(d1id);
+    double* Z = c->zero(zid) ? nullptr : c->tp(zid);
     if (!D1 || !Z) throw SccError(SCC_EDEVICE, "empty density");
     launch_deriv_contract(dh, N * N, D1, dchol, J * N * N, Z, ncoord, out, c->partials, c->s);
     return SCC_OK;
@@ -1519,7 +1668,9 @@ int scc_eval_residual(scc_ctx* c, const double* t, const double* zeta, const dou
         c->fill(c->tp(m.xs[k].r2), nov * nov, 0.0);
       }
     }
+    c->ex->set_lowp(c->opt.precision == 1);
     c->run(m.p_res);
+    c->ex->set_lowp(false);
     c->get(m.res.E, out);
     c->get(m.res.O1, out + 1);
     c->get(m.res.O2, out + 1 + nov);

@@ -3,6 +3,7 @@
 // eigensolver (Householder reduction to Hessenberg form, complex
 // single-shift QR with Wilkinson shifts, eigenvectors by inverse iteration).
 #pragma once
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -176,6 +177,57 @@ inline bool eig_nonsym(int n, const std::vector<double>& A, std::vector<cplx>& w
     for (int i = 0; i < n; ++i) V[i * n + k] = x[i] * ph;
   }
   return true;
+}
+
+// Symmetric eigenproblem A = V diag(w) V^T (row-major n x n) by cyclic
+// Jacobi rotations; eigenvalues ascending, eigenvectors in the columns of V.
+inline void eig_sym(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a(i, j) * a(i, j);
+        if (i != j) off += a(i, j) * a(i, j);
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a(p, q);
+        if (std::fabs(apq) < 1e-300) continue;
+        // rotation angle that zeroes a(p,q): tan(2 phi) = 2 a_pq / (a_qq - a_pp)
+        const double theta = (a(q, q) - a(p, p)) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a(k, p), akq = a(k, q);
+          a(k, p) = cs * akp - sn * akq;
+          a(k, q) = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a(p, k), aqk = a(q, k);
+          a(p, k) = cs * apk - sn * aqk;
+          a(q, k) = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+          V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
+  std::vector<double> W((size_t)n * n);
+  w.resize(n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = a(ord[j], ord[j]);
+    for (int i = 0; i < n; ++i) W[(size_t)i * n + j] = V[(size_t)i * n + ord[j]];
+  }
+  V.swap(W);
 }
 
 }  // namespace scc

@@ -152,3 +152,82 @@ def test_deterministic():
         assert np.array_equal(a[4][k], b[4][k])
     for k in a[5]:
         assert np.array_equal(a[5][k], b[5][k])
+
+
+def test_fp32_product_residual_is_close():
+    """Reduced-precision pass: FP32 products with FP32 accumulation in the
+    dense contractions keep the residual within single-precision error of
+    the FP64 oracle."""
+    import torch
+    from oracle import cc
+    from paper_2403_01007_amd import Context
+    from synth_inputs import random_amplitudes
+    S = make_system("o5v19", seed=7)
+    print("[fp32 residual o5v19]", flush=True)
+    h, L = S.at(np.zeros(S.ncoord))
+    ctx = Context(S.o, S.v, S.nj, S.nstates, precision="fp32")
+    ctx.set_hamiltonian(h, L)
+    t1, t2 = random_amplitudes(S.o, S.v, seed=5, scale=0.05)
+    out = ctx.eval_residual(np.concatenate([t1.ravel(), t2.ravel()])).cpu().numpy()
+    T = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float64)
+    g = np.einsum("Jpq,Jrs->pqrs", L, L)
+    E, s, d = cc.residual(T(h), T(g), T(t1), T(t2), S.o)
+    ref = np.concatenate([[float(E)], s.numpy().ravel(), d.numpy().ravel()])
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"  relative max error {err:.2e}", flush=True)
+    assert 1e-12 < err < 1e-5   # FP32 rounding is visible, and bounded
+
+
+@pytest.mark.parametrize("name", ["o2v4", "o4v12"])
+def test_fp32_then_fp64_refinement_matches_fp64(name):
+    """precision=1: the FP32-product pass followed by FP64 refinement reaches
+    the FP64 results to the FP64 tolerances."""
+    from paper_2403_01007_amd import Context
+    S = make_system(name)
+    print(f"[mixed {name}]", flush=True)
+    ref = _run_gpu(S)
+    h, L = S.at(np.zeros(S.ncoord))
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12, precision="fp32")
+    ctx.set_hamiltonian(h, L)
+    E, z, _ = ctx.excited()
+    assert np.abs(E - ref[2]).max() < E_TOL
+    for k in range(S.nstates):
+        assert np.abs(ctx.gradient(k, S.dh, S.dL)[0] - ref[4][k]).max() < G_TOL
+    for (m, n) in S.nacs:
+        assert np.abs(ctx.nac(m, n, S.dh, S.dL)[0] - ref[5][(m, n)]).max() < G_TOL
+
+
+def test_fixed_basis_displaced_geometry():
+    """Hamiltonian given in the fixed basis at a displaced geometry: RHF on
+    the device, then energies, gradients and couplings (derivative integrals
+    in the fixed basis) against the oracle's RHF + SCCSD at the same x."""
+    import torch
+    from oracle import scc as oscc
+    from paper_2403_01007_amd import Context
+    S = make_system("o2v4")
+    x = 0.05 * np.random.default_rng(3).normal(size=S.ncoord)
+    print("[fixed basis o2v4, displaced]", flush=True)
+    h, L = S.at(x)
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
+    C, info = ctx.set_hamiltonian_fixed_basis(h, L)
+    E, z, _ = ctx.excited()
+    sol = oscc.solve_system(S, x=x)
+    assert np.abs(C.cpu().numpy() - np.asarray(sol.C)).max() < 1e-9
+    assert np.abs(E - np.asarray(sol.E)).max() < E_TOL
+    targets = [("grad", k) for k in range(S.nstates)]
+    for (m, n) in S.nacs:
+        targets += [("nac", m, n), ("nac", n, m)]
+    ref = oscc.gradient_and_nacs(S, sol, targets)
+    for k in range(S.nstates):
+        err = np.abs(ctx.gradient(k, S.dh, S.dL)[0] - ref[("grad", k)]["value"]).max()
+        print(f"  grad {k} max err {err:.2e}", flush=True)
+        assert err < G_TOL
+    for (m, n) in S.nacs:
+        for a, b in [(m, n), (n, m)]:
+            err = np.abs(ctx.nac(a, b, S.dh, S.dL)[0] - ref[("nac", a, b)]["value"]).max()
+            print(f"  nac {(a, b)} max err {err:.2e}", flush=True)
+            assert err < G_TOL
+    # densities come back in the fixed basis
+    d1, z3, kb = ctx.densities()
+    d1_ref = ref[("nac", S.nacs[0][1], S.nacs[0][0])]["D1"]
+    assert np.abs(d1.cpu().numpy() - d1_ref).max() < 1e-9 * max(1.0, np.abs(d1_ref).max())
