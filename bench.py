@@ -20,6 +20,112 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 
 
+def learned_main(args):
+    """Learned initial guesses on the trajectory family H(x) = H0 + sum_k x_k H_k:
+    solve the training geometries, fit PCA bases of the amplitudes and of the
+    excited-state vectors on the device, train the perceptron on the device,
+    then time held-out geometries with the plain start and with the predicted
+    start (every prediction judged by the solvers' residuals)."""
+    import numpy as np
+    import torch
+    from paper_2403_01007_amd import Context
+    from paper_2403_01007_amd.binding import FIELD_R, FIELD_T, Mlp, pca_expand, pca_fit
+    from synth_inputs import family_geometries, make_system
+
+    S = make_system(args.learned_workload)
+    dev = torch.device("cuda:0")
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11)
+    ns, npair = S.nstates, S.nstates * (S.nstates - 1) // 2
+
+    def solve(x, guess=None):
+        h, L = S.at(x)
+        ctx.set_hamiltonian_fixed_basis(torch.as_tensor(h, device=dev), torch.as_tensor(L, device=dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it_g = 0
+        fb = 0
+        if guess is not None:
+            tg, rg = guess
+            _, info = ctx.ground(tg)
+            it_g, fb = info.iterations, info.fallback_used
+        E, z, info = ctx.excited(None if guess is None else rg)
+        t_exc = time.perf_counter() - t0
+        for n in range(ns):
+            ctx.gradient(n, dh, dL)
+        for (m, n) in S.nacs:
+            ctx.nac(m, n, dh, dL)
+        torch.cuda.synchronize()
+        return dict(E=np.asarray(E), zeta=np.asarray(z), t_exc=t_exc, t_all=time.perf_counter() - t0,
+                    iters=info.iterations + it_g, fallback=fb or info.fallback_used)
+
+    dh = torch.as_tensor(S.dh, device=dev)
+    dL = torch.as_tensor(S.dL, device=dev)
+    Xtr = family_geometries(S.ncoord, range(10000, 10000 + args.ntrain))
+    Xte = family_geometries(S.ncoord, range(20000, 20000 + args.nheld))
+    nst = 1 + S.o * S.v * (1 + S.o * S.v)
+    Tm = torch.empty((args.ntrain, nst - 1), dtype=torch.float64, device=dev)
+    Rm = torch.empty((args.ntrain, ns * nst), dtype=torch.float64, device=dev)
+    Zm = np.zeros((args.ntrain, npair))
+    t0 = time.perf_counter()
+    for i, x in enumerate(Xtr):
+        r = solve(x)
+        Tm[i] = ctx.get(FIELD_T)
+        for k in range(ns):
+            Rm[i, k * nst:(k + 1) * nst] = ctx.get(FIELD_R, k)
+        Zm[i] = r["zeta"]
+    t_data = time.perf_counter() - t0
+    print(f"[learned: {args.ntrain} training geometries solved in {t_data:.1f} s]", file=sys.stderr, flush=True)
+    kt = min(64, args.ntrain - 1)
+    mt, Ut, Ct, _ = pca_fit(Tm, kt)
+    mr, Ur, Cr, _ = pca_fit(Rm, kt)
+    Y = np.concatenate([Ct.cpu().numpy(), Cr.cpu().numpy(), Zm], axis=1)
+    nout = Y.shape[1]
+    rng = np.random.Generator(np.random.PCG64(4242))
+    nh = 256
+    sizes = [(nh, S.ncoord), (nh,), (nh, nh), (nh,), (nout, nh), (nout,)]
+    p0 = np.concatenate([rng.normal(0, 1.0 / np.sqrt(sh[1]), size=sh).ravel() if len(sh) == 2 else np.zeros(sh)
+                         for sh in sizes])
+    net = Mlp(S.ncoord, nh, nout, p0)
+    batch = min(64, args.ntrain)
+    order = np.stack([rng.permutation(args.ntrain)[:batch] for _ in range(args.train_steps)])
+    t1 = time.perf_counter()
+    losses = net.train(Xtr, Y, order, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    print(f"[learned: trained {args.train_steps} steps in {t_train:.2f} s, loss {losses[0]:.3e} -> "
+          f"{losses[-20:].mean():.3e}]", file=sys.stderr, flush=True)
+    plain, learned = [], []
+    for x in Xte:
+        plain.append(solve(x))
+        c0 = time.perf_counter()
+        yp = net.forward(x[None, :]).to(torch.float64)
+        tg = pca_expand(mt, Ut, yp[:, :kt])[0]
+        rg = pca_expand(mr, Ur, yp[:, kt:2 * kt])[0]
+        guess_r = torch.cat([rg, yp[0, 2 * kt:]])
+        t_pred = time.perf_counter() - c0
+        r = solve(x, (tg, guess_r))
+        r["t_exc"] += t_pred
+        r["t_all"] += t_pred
+        learned.append(r)
+    dE = max(float(np.abs(a["E"] - b["E"]).max()) for a, b in zip(plain, learned))
+    mean = lambda rs, key: float(np.mean([r[key] for r in rs]))
+    line = {
+        "metric": "s/geometry (energies+gradients+NACs), MFMA TFLOP/s; mixed+learned vs FP64",
+        "value": mean(learned, "t_all"), "unit": "s/geometry", "n_gpus": 1, "steps": args.nheld, "warmup": 0,
+        "ms_per_step": 1e3 * mean(learned, "t_all"), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.learned_workload, "guess": "learned", "ntrain": args.ntrain,
+                   "nheld": args.nheld, "pca": kt, "mlp": [S.ncoord, nh, nh, nout]},
+        "learned": {"plain_s_per_geometry": mean(plain, "t_all"), "learned_s_per_geometry": mean(learned, "t_all"),
+                    "plain_excited_s": mean(plain, "t_exc"), "learned_excited_s": mean(learned, "t_exc"),
+                    "plain_iterations": mean(plain, "iters"), "learned_iterations": mean(learned, "iters"),
+                    "fallbacks": int(sum(r["fallback"] for r in learned)), "max_abs_energy_diff": dE,
+                    "training_data_s": t_data, "training_s": t_train,
+                    "final_loss": float(losses[-20:].mean())},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -33,11 +139,22 @@ def main():
                          "largest differences and the FP64 time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no HIP graphs)")
+    ap.add_argument("--no-roofline", action="store_true", help="no per-GEMM event timing in the timed region")
+    ap.add_argument("--learned", action="store_true",
+                    help="learned initial guesses: train on the trajectory family, time held-out geometries")
+    ap.add_argument("--learned-workload", default="o4v12x36")
+    ap.add_argument("--ntrain", type=int, default=200)
+    ap.add_argument("--nheld", type=int, default=20)
+    ap.add_argument("--train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.learned:
+        learned_main(args)
+        return
     import numpy as np
     import torch
     from paper_2403_01007_amd import Context
@@ -47,7 +164,7 @@ def main():
     h, L = S.at(np.zeros(S.ncoord))
     dev = torch.device("cuda:0")
     ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11, verbose=args.verbose,
-                  precision=args.precision)
+                  precision=args.precision, eager=args.eager)
     h_d = torch.as_tensor(h, device=dev)
     L_d = torch.as_tensor(L, device=dev)
     dh = torch.as_tensor(S.dh, device=dev)
@@ -92,7 +209,7 @@ def main():
         step()
         print(f"[warmup step done]", file=sys.stderr, flush=True)
     flops[0] = 0.0
-    ms0, fl0, n0 = ctx.profile(True)
+    ms0, fl0, n0 = ctx.profile(not args.no_roofline)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):

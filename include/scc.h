@@ -26,9 +26,11 @@
  *     workspace; the library never allocates device memory and never keeps a
  *     caller pointer after a call returns (the Hamiltonian is copied into the
  *     workspace).
- *   - All work is enqueued on the stream given to scc_create; calls are
- *     blocking (they synchronise that stream before returning) because the
- *     solvers read residual norms back to the host.
+ *   - Every call orders its work after the work already enqueued on the
+ *     stream given to scc_create, runs it on a stream of the context's own
+ *     (created with default priority) and is blocking: it synchronises that
+ *     stream before returning, because the solvers read residual norms back
+ *     to the host.  Outputs are complete when a call returns.
  *
  * Errors: every int-returning call returns one of the SCC_* codes below and
  * never throws.  On error, outputs other than scc_info are unspecified and
@@ -75,10 +77,16 @@ typedef struct scc_options {
                             solve is then refined in FP64 from that point.
                             Residual norms, DIIS, subspace eigenproblems and
                             orthogonalisation stay in FP64 in both modes. */
+  int eager;             /* 0: every device program (the residual, the
+                            transformations, the Lagrangian products...) is
+                            captured once as a HIP graph and replayed.
+                            1: kernels are launched one by one.  Results are
+                            identical. */
 } scc_options;
 
 typedef struct scc_info {
-  int iterations;        /* solver iterations of the call */
+  int iterations;        /* solver iterations of the call (ground-state steps plus
+                            Davidson steps, or Krylov steps) */
   int converged;         /* 1 on success */
   int fallback_used;     /* 1 if a supplied guess was rejected */
   double residual;       /* final residual norm */
@@ -130,7 +138,10 @@ int scc_set_hamiltonian_fixed_basis(scc_ctx* ctx, const double* h, const double*
                                     const double* orbitals_guess, double* orbitals, scc_info* info);
 
 /* Ground state Omega(t) = 0 of CCSD (zeta = 0) (coupled cluster section,
- * eq. for Omega_mu).  guess_t: NULL or [t1 | t2]; e0: device double[1]. */
+ * eq. for Omega_mu).  guess_t: NULL or [t1 | t2]; a guess is used only if
+ * its residual norm is below that of the plain start (the MP2 amplitudes),
+ * else info->fallback_used = 1.  e0: device double[1].  The converged
+ * amplitudes are the starting point of a following scc_excited. */
 int scc_ground(scc_ctx* ctx, const double* guess_t, double* e0, scc_info* info);
 
 /* Excited states of the constrained set: EOM right/left eigenvectors with the
@@ -139,7 +150,12 @@ int scc_ground(scc_ctx* ctx, const double* guess_t, double* e0, scc_info* info);
  * section; natural projection).  Normalisation: O_kk = 1 and calL_k.calR_k =
  * 1; phase: largest |R1| element positive; order: ascending energy.
  * energies: device double[nstates] (total energies);
- * zeta: device double[nstates*(nstates-1)/2] (pairs k<l, row-major). */
+ * zeta: device double[nstates*(nstates-1)/2] (pairs k<l, row-major).
+ * guess: NULL (plain start: CCSD states at zeta = 0 from unit vectors on
+ * the lowest singles) or [nstates][1 + nov + nov^2] right vectors followed
+ * by [npairs] zeta values; the solve then starts there (amplitudes from the
+ * preceding scc_ground or scc_excited) and falls back to the plain start,
+ * with info->fallback_used = 1, if it does not converge. */
 int scc_excited(scc_ctx* ctx, int nstates, const double* guess, double* energies, double* zeta, scc_info* info);
 
 /* Lagrange multipliers of the gradient of state n (kind = 0, m ignored) or

@@ -15,7 +15,9 @@ FIELD_T, FIELD_R, FIELD_L, FIELD_E0, FIELD_OMEGA = 0, 1, 2, 3, 4
 EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_last_error",
                     "scc_set_hamiltonian", "scc_set_hamiltonian_fixed_basis", "scc_ground", "scc_excited", "scc_multipliers",
                     "scc_densities", "scc_gradient", "scc_nac", "scc_get", "scc_eval_residual",
-                    "scc_eval_sigma", "scc_eval_left", "scc_profile"]
+                    "scc_eval_sigma", "scc_eval_left", "scc_profile",
+                    "scc_mlp_param_count", "scc_mlp_workspace_bytes", "scc_mlp_forward", "scc_mlp_loss_grad",
+                    "scc_mlp_train", "scc_pca_workspace_bytes", "scc_pca_fit", "scc_pca_expand"]
 
 
 class Dims(ctypes.Structure):
@@ -26,12 +28,16 @@ class Dims(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("tol_residual", ctypes.c_double), ("tol_overlap", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("scc", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("eager", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("fallback_used", ctypes.c_int),
                 ("residual", ctypes.c_double), ("seconds", ctypes.c_double), ("flops_mfma", ctypes.c_double)]
+
+
+class MlpDims(ctypes.Structure):
+    _fields_ = [("nin", ctypes.c_int), ("nhidden", ctypes.c_int), ("nout", ctypes.c_int)]
 
 
 class SccError(RuntimeError):
@@ -73,6 +79,15 @@ def load_library():
     lib.scc_eval_sigma.argtypes = [P, P, P]
     lib.scc_eval_left.argtypes = [P, P, P]
     lib.scc_profile.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]
+    MD = ctypes.POINTER(MlpDims)
+    lib.scc_mlp_param_count.argtypes = [MD, ctypes.POINTER(ctypes.c_longlong)]
+    lib.scc_mlp_workspace_bytes.argtypes = [MD, I, ctypes.POINTER(S)]
+    lib.scc_mlp_forward.argtypes = [MD, P, I, P, P, P, S, P]
+    lib.scc_mlp_loss_grad.argtypes = [MD, P, I, P, P, P, P, P, S, P]
+    lib.scc_mlp_train.argtypes = [MD, P, P, P, I, P, P, I, I, P, ctypes.c_float, I, P, P, S, P]
+    lib.scc_pca_workspace_bytes.argtypes = [I, ctypes.c_longlong, I, ctypes.POINTER(S)]
+    lib.scc_pca_fit.argtypes = [I, ctypes.c_longlong, I, P, P, P, P, P, P, S, P]
+    lib.scc_pca_expand.argtypes = [I, ctypes.c_longlong, I, P, P, P, P, P]
     for name in EXPORTED_SYMBOLS:
         fn = getattr(lib, name)
         if name not in ("scc_destroy", "scc_last_error"):
@@ -99,7 +114,7 @@ class Context:
     """Owns a libscc context plus its workspace (a torch uint8 CUDA tensor)."""
 
     def __init__(self, o, v, nj, nstates, tol=1e-10, tol_overlap=1e-11, max_iter=200, scc=True,
-                 verbose=False, device="cuda:0", stream=None, precision="fp64"):
+                 verbose=False, device="cuda:0", stream=None, precision="fp64", eager=False):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -110,7 +125,7 @@ class Context:
         if precision not in ("fp64", "fp32"):
             raise ValueError("precision must be 'fp64' or 'fp32'")
         self.opts = Options(tol, tol_overlap, max_iter, 1 if scc else 0, 1 if verbose else 0,
-                            1 if precision == "fp32" else 0)
+                            1 if precision == "fp32" else 0, 1 if eager else 0)
         self.dims = Dims(o, v, nj, nstates)
         nbytes = ctypes.c_size_t(0)
         self._check(self.lib.scc_workspace_bytes(ctypes.byref(self.dims), ctypes.byref(self.opts),
@@ -176,11 +191,13 @@ class Context:
         self._check(self.lib.scc_ground(self.h, _ptr(g), _ptr(e0), ctypes.byref(info)), "scc_ground")
         return float(e0.cpu()[0]), info
 
-    def excited(self):
+    def excited(self, guess=None):
+        """guess: None or [ns * (1 + nov + nov^2) + npairs] (right vectors, then zeta)."""
         e = self.zeros(self.ns)
         z = self.zeros(max(1, self.ns * (self.ns - 1) // 2))
         info = Info()
-        self._check(self.lib.scc_excited(self.h, self.ns, None, _ptr(e), _ptr(z), ctypes.byref(info)),
+        g = None if guess is None else self._dev(guess)
+        self._check(self.lib.scc_excited(self.h, self.ns, _ptr(g), _ptr(e), _ptr(z), ctypes.byref(info)),
                     "scc_excited")
         return e.cpu().numpy(), z.cpu().numpy()[:self.ns * (self.ns - 1) // 2], info
 
@@ -245,3 +262,104 @@ class Context:
         v = self._dev(vec)
         self._check(self.lib.scc_eval_left(self.h, _ptr(v), _ptr(out)), "scc_eval_left")
         return out
+
+
+# --- learned initial-guess model (include/scc_learn.h) -------------------------
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _chk(rc, what):
+    if rc != SCC_OK:
+        raise SccError(rc, what)
+
+
+class Mlp:
+    """Tanh perceptron (nin, nhidden, nhidden, nout) in FP32 on the device;
+    params is a flat float32 CUDA tensor [W1|b1|W2|b2|W3|b3]."""
+
+    def __init__(self, nin, nhidden, nout, params, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.d = MlpDims(nin, nhidden, nout)
+        n = ctypes.c_longlong(0)
+        _chk(self.lib.scc_mlp_param_count(ctypes.byref(self.d), ctypes.byref(n)), "scc_mlp_param_count")
+        self.count = n.value
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(device).contiguous().clone()
+        assert self.params.numel() == self.count
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.steps = 0
+        self.device = device
+
+    def _ws(self, batch):
+        b = ctypes.c_size_t(0)
+        _chk(self.lib.scc_mlp_workspace_bytes(ctypes.byref(self.d), batch, ctypes.byref(b)), "workspace")
+        return self.torch.empty(b.value + 8 * (batch * (self.d.nin + self.d.nout) + self.count + 64),
+                                dtype=self.torch.uint8, device=self.device)
+
+    def _f32(self, a):
+        return self.torch.as_tensor(a, dtype=self.torch.float32).to(self.device).contiguous()
+
+    def forward(self, X):
+        X = self._f32(X)
+        Y = self.torch.empty((X.shape[0], self.d.nout), dtype=self.torch.float32, device=self.device)
+        ws = self._ws(X.shape[0])
+        _chk(self.lib.scc_mlp_forward(ctypes.byref(self.d), _ptr(self.params), X.shape[0], _ptr(X), _ptr(Y), _ptr(ws),
+                                      ws.numel(), _stream()), "scc_mlp_forward")
+        return Y
+
+    def loss_grad(self, X, T):
+        X, T = self._f32(X), self._f32(T)
+        loss = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
+        g = self.torch.empty_like(self.params)
+        ws = self._ws(X.shape[0])
+        _chk(self.lib.scc_mlp_loss_grad(ctypes.byref(self.d), _ptr(self.params), X.shape[0], _ptr(X), _ptr(T),
+                                        _ptr(loss), _ptr(g), _ptr(ws), ws.numel(), _stream()), "scc_mlp_loss_grad")
+        return float(loss.cpu()[0]), g
+
+    def train(self, X, T, order, lr=1e-3):
+        """order: int array [nsteps][batch] of sample indices."""
+        import numpy as np
+        X, T = self._f32(X), self._f32(T)
+        order = np.asarray(order, dtype=np.int32)
+        nsteps, batch = order.shape
+        od = self.torch.as_tensor(order).to(self.device).contiguous()
+        losses = self.torch.zeros(nsteps, dtype=self.torch.float32, device=self.device)
+        ws = self._ws(batch)
+        _chk(self.lib.scc_mlp_train(ctypes.byref(self.d), _ptr(self.params), _ptr(self.m), _ptr(self.v), X.shape[0],
+                                    _ptr(X), _ptr(T), nsteps, batch, _ptr(od), float(lr), self.steps, _ptr(losses),
+                                    _ptr(ws), ws.numel(), _stream()), "scc_mlp_train")
+        self.steps += nsteps
+        return losses.cpu().numpy()
+
+
+def pca_fit(X, k):
+    """X: float64 CUDA tensor [n][d] -> (mean [d], basis [k][d], coef [n][k], eigenvalues [k] host)."""
+    import torch
+    lib = load_library()
+    X = X.to(torch.float64).contiguous()
+    n, d = X.shape
+    b = ctypes.c_size_t(0)
+    _chk(lib.scc_pca_workspace_bytes(n, d, k, ctypes.byref(b)), "scc_pca_workspace_bytes")
+    ws = torch.empty(b.value, dtype=torch.uint8, device=X.device)
+    mean = torch.empty(d, dtype=torch.float64, device=X.device)
+    basis = torch.empty((k, d), dtype=torch.float64, device=X.device)
+    coef = torch.empty((n, k), dtype=torch.float64, device=X.device)
+    w = (ctypes.c_double * k)()
+    _chk(lib.scc_pca_fit(n, d, k, _ptr(X), _ptr(mean), _ptr(basis), _ptr(coef), ctypes.cast(w, ctypes.c_void_p),
+                         _ptr(ws), ws.numel(), _stream()), "scc_pca_fit")
+    return mean, basis, coef, list(w)
+
+
+def pca_expand(mean, basis, coef):
+    import torch
+    lib = load_library()
+    coef = coef.to(torch.float64).contiguous()
+    m, k = coef.shape
+    d = mean.numel()
+    out = torch.empty((m, d), dtype=torch.float64, device=mean.device)
+    _chk(lib.scc_pca_expand(m, d, k, _ptr(mean), _ptr(basis), _ptr(coef), _ptr(out), _stream()), "scc_pca_expand")
+    return out

@@ -474,9 +474,89 @@ void launch_combine(const double* X, int k, int64_t n, const double* coef, doubl
   check(hipGetLastError(), "combine launch");
 }
 
-void launch_perm(const PermArgs& a, hipStream_t s) {
-  if (a.total <= 0) return;
-  hipLaunchKernelGGL(perm_kernel, dim3(grid_for(a.total)), dim3(256), 0, s, a);
+// Index arithmetic of the permutation kernel in 32 bits: n / d for
+// n, d < 2^31 as (umulhi(n, m) + n) >> s with s = ceil(log2 d) and
+// m = floor(2^32 (2^s - d) / d) + 1 (round-up multiplier).
+struct FastPerm {
+  PermArgs a;
+  uint32_t dim[MAXD], mag[MAXD], sh[MAXD];
+};
+
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t m, uint32_t s) {
+  return (__umulhi(n, m) + n) >> s;
+}
+
+template <int NIN>
+__global__ __launch_bounds__(256) void perm_fast_kernel(FastPerm f) {
+  const PermArgs& a = f.a;
+  const uint32_t total = (uint32_t)a.total;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t lin = blockIdx.x * blockDim.x + threadIdx.x; lin < total; lin += stride) {
+    uint32_t rem = lin;
+    int64_t oo = 0;
+    int64_t io[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) io[i] = 0;
+#pragma unroll
+    for (int d = MAXD - 1; d >= 0; --d) {
+      if (d < a.nd) {
+        const uint32_t q = fast_div(rem, f.mag[d], f.sh[d]);
+        const int64_t x = (int64_t)(rem - q * f.dim[d]);
+        rem = q;
+        oo += x * a.ostr[d];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) io[i] += x * a.istr[i][d];
+      }
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) v += a.coef[i] * a.in[i][io[i]];
+    if (a.addend) v += a.beta * a.addend[oo];
+    a.out[oo] = v;
+  }
+}
+
+void launch_perm(const PermArgs& in, hipStream_t s) {
+  if (in.total <= 0) return;
+  // merge neighbouring dimensions that are contiguous in the output and in
+  // every input (fewer index digits per element)
+  PermArgs a = in;
+  for (int d = a.nd - 2; d >= 0; --d) {
+    bool ok = a.ostr[d] == a.ostr[d + 1] * a.dim[d + 1];
+    for (int i = 0; i < a.nin; ++i) ok = ok && a.istr[i][d] == a.istr[i][d + 1] * a.dim[d + 1];
+    if (!ok) continue;
+    a.dim[d] *= a.dim[d + 1];
+    a.ostr[d] = a.ostr[d + 1];
+    for (int i = 0; i < a.nin; ++i) a.istr[i][d] = a.istr[i][d + 1];
+    for (int e = d + 1; e + 1 < a.nd; ++e) {
+      a.dim[e] = a.dim[e + 1];
+      a.ostr[e] = a.ostr[e + 1];
+      for (int i = 0; i < a.nin; ++i) a.istr[i][e] = a.istr[i][e + 1];
+    }
+    --a.nd;
+  }
+  const int64_t lim = (int64_t)1 << 31;
+  if (a.total < lim && a.nin >= 1 && a.nin <= 4) {
+    FastPerm f{};
+    f.a = a;
+    for (int d = 0; d < a.nd; ++d) {
+      const uint64_t dd = (uint64_t)a.dim[d];
+      uint32_t sh = 0;
+      while ((1ull << sh) < dd) ++sh;
+      f.dim[d] = (uint32_t)dd;
+      f.sh[d] = sh;
+      f.mag[d] = (uint32_t)(((1ull << 32) * ((1ull << sh) - dd)) / dd + 1);
+    }
+    const dim3 grid(grid_for(a.total)), block(256);
+    switch (a.nin) {
+      case 1: hipLaunchKernelGGL(perm_fast_kernel<1>, grid, block, 0, s, f); break;
+      case 2: hipLaunchKernelGGL(perm_fast_kernel<2>, grid, block, 0, s, f); break;
+      case 3: hipLaunchKernelGGL(perm_fast_kernel<3>, grid, block, 0, s, f); break;
+      default: hipLaunchKernelGGL(perm_fast_kernel<4>, grid, block, 0, s, f); break;
+    }
+  } else {
+    hipLaunchKernelGGL(perm_kernel, dim3(grid_for(a.total)), dim3(256), 0, s, a);
+  }
   check(hipGetLastError(), "perm launch");
 }
 
@@ -845,6 +925,27 @@ void Executor::plan_all() {
 
 Executor::~Executor() {
   for (auto& e : ev_) (void)hipEventDestroy(e);
+  for (auto& kv : graphs_cache_) {
+    for (auto& e : kv.second.ev) (void)hipEventDestroy(e);
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+}
+
+void Executor::account(double ms, double flops, const std::array<int64_t, 5>& shape, bool f32) {
+  if (f32) {
+    f32_ms += ms;
+    f32_flops += flops;
+    ++f32_launches;
+    return;
+  }
+  gemm_ms += ms;
+  gemm_flops += flops;
+  ++gemm_launches;
+  ShapeStat& st = shapes_[shape];
+  st.n += 1;
+  st.ms += ms;
+  st.flops += flops;
 }
 
 void Executor::set_profile(bool on) {
@@ -865,24 +966,28 @@ void Executor::flush_profile() {
   for (size_t i = 0; i < nev_; ++i) {
     float ms = 0;
     check(hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]), "event elapsed");
-    if (ev_f32_[i]) {
-      f32_ms += ms;
-      f32_flops += ev_flops_[i];
-      ++f32_launches;
-      continue;
-    }
-    gemm_ms += ms;
-    gemm_flops += ev_flops_[i];
-    ++gemm_launches;
-    ShapeStat& st = shapes_[ev_shape_[i]];
-    st.n += 1;
-    st.ms += ms;
-    st.flops += ev_flops_[i];
+    account(ms, ev_flops_[i], ev_shape_[i], ev_f32_[i] != 0);
   }
   nev_ = 0;
 }
 
 void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32) {
+  if (cap_) {
+    // inside a graph capture: event pairs of the graph's own
+    hipEvent_t e0, e1;
+    check(hipEventCreate(&e0), "event create");
+    check(hipEventCreate(&e1), "event create");
+    cap_->ev.push_back(e0);
+    cap_->ev.push_back(e1);
+    check(hipEventRecord(e0, s), "event record");
+    launch_gemm_main(g, s, f32);
+    check(hipEventRecord(e1, s), "event record");
+    launch_gemm_reduce(g, s);
+    cap_->flops.push_back(2.0 * g.M * g.N * g.K * g.batch);
+    cap_->shape.push_back({g.M, g.N, g.K, g.batch, g.splits});
+    cap_->f32.push_back(f32 ? 1 : 0);
+    return;
+  }
   if (nev_ == ev_flops_.size()) flush_profile();
   // the events bracket the MFMA kernel alone (a split-K reduction follows)
   check(hipEventRecord(ev_[2 * nev_], s), "event record");
@@ -922,7 +1027,43 @@ double Executor::flops(const std::vector<int>& list) const {
 }
 
 void Executor::run(const std::vector<int>& list, hipStream_t s) {
-  for (int k : list) run_op(k, s);
+  if (!graphs_ || prof_ || list.empty()) {
+    for (int k : list) run_op(k, s);
+    return;
+  }
+  const std::array<int64_t, 3> key = {(int64_t)(intptr_t)&list, lowp_ ? 1 : 0, prof_ ? 1 : 0};
+  auto it = graphs_cache_.find(key);
+  if (it == graphs_cache_.end()) {
+    flush_profile();
+    Captured c;
+    cap_ = &c;
+    check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture begin");
+    try {
+      for (int k : list) run_op(k, s);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      cap_ = nullptr;
+      for (auto& e : c.ev) (void)hipEventDestroy(e);
+      throw;
+    }
+    cap_ = nullptr;
+    check(hipStreamEndCapture(s, &c.graph), "graph capture end");
+    check(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0), "graph instantiate");
+    it = graphs_cache_.emplace(key, std::move(c)).first;
+  }
+  Captured& c = it->second;
+  check(hipGraphLaunch(c.exec, s), "graph launch");
+  if (prof_ && !c.ev.empty()) {
+    // the event nodes are re-recorded by the next replay: read them now
+    check(hipStreamSynchronize(s), "graph profile sync");
+    for (size_t i = 0; i < c.flops.size(); ++i) {
+      float ms = 0;
+      check(hipEventElapsedTime(&ms, c.ev[2 * i], c.ev[2 * i + 1]), "event elapsed");
+      account(ms, c.flops[i], c.shape[i], c.f32[i] != 0);
+    }
+  }
 }
 
 void Executor::run_op(int k, hipStream_t s) {

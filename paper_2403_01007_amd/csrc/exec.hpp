@@ -125,6 +125,10 @@ class Executor {
   // reduced precision: dense contractions (M, N, K >= 64) take FP32 products
   void set_lowp(bool on) { lowp_ = on; }
   bool lowp() const { return lowp_; }
+  // Graph mode: each op list is captured once (per precision and profiling
+  // setting) as a HIP graph and replayed; every tensor lives at a fixed
+  // arena address, so the captured kernel arguments stay valid.
+  void set_graphs(bool on) { graphs_ = on; }
   // per-shape totals of the timed launches, largest time first
   void shape_report(FILE* f, int top) const;
   ~Executor();
@@ -136,7 +140,19 @@ class Executor {
   int64_t scratch_n_;
   double* partials_;
   std::vector<ContractPlan> plans_;
-  bool prof_ = false, lowp_ = false;
+  bool prof_ = false, lowp_ = false, graphs_ = false;
+  struct Captured {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // profiling variant: event pairs around the GEMM nodes
+    std::vector<hipEvent_t> ev;
+    std::vector<double> flops;
+    std::vector<std::array<int64_t, 5>> shape;
+    std::vector<char> f32;
+  };
+  std::map<std::array<int64_t, 3>, Captured> graphs_cache_;
+  Captured* cap_ = nullptr;  // set while a graph is being captured
+  void account(double ms, double flops, const std::array<int64_t, 5>& shape, bool f32);
   std::vector<char> ev_f32_;
   std::vector<hipEvent_t> ev_;
   std::vector<double> ev_flops_;

@@ -88,7 +88,17 @@ struct scc_ctx {
   Model m;
   Sizes sz{};
   std::unique_ptr<Executor> ex;
+  // all work runs on a stream of the context's own (graph capture needs a
+  // stream other than the legacy default stream), ordered after the work
+  // already enqueued on the caller's stream at the start of every call
   hipStream_t s = nullptr;
+  hipStream_t user_s = nullptr;
+  hipEvent_t entry_ev = nullptr;
+  ~scc_ctx() {
+    ex.reset();
+    if (entry_ev) (void)hipEventDestroy(entry_ev);
+    if (s) (void)hipStreamDestroy(s);
+  }
   double* arena = nullptr;
   double* scratch = nullptr;
   int64_t scratch_n = 0;
@@ -109,6 +119,7 @@ struct scc_ctx {
   bool scc_on = false;        // the SCC constraint (zeta, O_kl) is part of the solution
   std::vector<double> Jz;     // zeta Jacobian dO/dzeta of the last SCC solve
   bool fixed_basis = false;   // Hamiltonian (and derivative integrals) in a fixed basis
+  int last_ground_its = 0;    // iterations of the last ground-state solve
   double E0 = 0.0, enuc = 0.0;
   std::vector<double> E, zeta;
   int mult_kind = -1, mult_m = -1, mult_n = -1;
@@ -144,11 +155,16 @@ struct scc_ctx {
       cp(dst, tp(id), n);
   }
   void put(int id, const double* src) { cp(tp(id), src, m.g.t[id].size()); }
+  // copy on the context's stream and wait for it (host buffers may be
+  // pageable and short-lived)
+  void xfer(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);
+    if (e != hipSuccess) throw SccError(SCC_EDEVICE, std::string("hip: ") + hipGetErrorString(e));
+    sync();
+  }
   double host_scalar(const double* dp) {
     double v = 0;
-    sync();
-    hipError_t e = hipMemcpy(&v, dp, sizeof(double), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) throw SccError(SCC_EDEVICE, "memcpy d2h");
+    xfer(&v, dp, sizeof(double), hipMemcpyDeviceToHost);
     return v;
   }
   double tensor_scalar(int id) { return zero(id) ? 0.0 : host_scalar(tp(id)); }
@@ -214,6 +230,7 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
     c->sym_doubles(r + nov);
     rn = std::sqrt(c->dot(r, r, nvt));
     c->log("  ground it %3d  |Omega| %.3e\n", it, rn);
+    c->last_ground_its = it;
     if (rn < tol) break;
     // restart the extrapolation when it stagnates
     if (rn < best) {
@@ -270,7 +287,7 @@ std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, co
   double* tmp = c->alloc(k);
   launch_deriv_contract(Cb, n, r, Cb, 0, r, k, tmp, c->partials, c->s);
   c->sync();
-  hck(hipMemcpy(h.data(), tmp, k * sizeof(double), hipMemcpyDeviceToHost));
+  c->xfer(h.data(), tmp, k * sizeof(double), hipMemcpyDeviceToHost);
   c->pool_used -= up(k);
   (void)dout;
   return h;
@@ -280,7 +297,7 @@ std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, co
 void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* devcoef,
                 double* y) {
   if (k == 0) return;
-  hck(hipMemcpyAsync(devcoef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice, c->s));
+  c->xfer(devcoef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice);
   launch_combine(Xb, k, n, devcoef, y, c->s);
 }
 
@@ -393,7 +410,7 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
   if (nv < nwork) {
     // unit vectors on the smallest singles denominators
     std::vector<double> dh(nov);
-    hck(hipMemcpy(dh.data(), c->D, nov * sizeof(double), hipMemcpyDeviceToHost));
+    c->xfer(dh.data(), c->D, nov * sizeof(double), hipMemcpyDeviceToHost);
     std::vector<int> idx(nov);
     for (int64_t i = 0; i < nov; ++i) idx[i] = (int)i;
     std::sort(idx.begin(), idx.end(), [&](int a, int b) { return dh[a] < dh[b]; });
@@ -529,6 +546,7 @@ int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& ite
   double rn = 0;
   int rc = ground_solve(c, tol, maxit, rn);
   if (rc) return rc;
+  iters += c->last_ground_its;
   c->E0 = c->tensor_scalar(m.res.E);
   c->run(m.p_sig_pre);
   std::vector<const double*> gr, gl;
@@ -580,7 +598,7 @@ int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& ite
     } else {
       std::vector<double> r1(nov);
       c->sync();
-      hck(hipMemcpy(r1.data(), outR[k] + 1, nov * sizeof(double), hipMemcpyDeviceToHost));
+      c->xfer(r1.data(), outR[k] + 1, nov * sizeof(double), hipMemcpyDeviceToHost);
       int64_t im = 0;
       for (int64_t i = 1; i < nov; ++i)
         if (std::fabs(r1[i]) > std::fabs(r1[im])) im = i;
@@ -1120,13 +1138,13 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
     c->run(m.p_dens);
     std::vector<double> dh((size_t)m.d.n * m.d.n);
     c->sync();
-    if (!c->zero(m.dens_hk)) hck(hipMemcpy(dh.data(), c->tp(m.dens_hk), dh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (!c->zero(m.dens_hk)) c->xfer(dh.data(), c->tp(m.dens_hk), dh.size() * sizeof(double), hipMemcpyDeviceToHost);
     std::vector<double> ck(nov);
     const int o = m.d.o, v = m.d.v, N = m.d.n;
     for (int a = 0; a < v; ++a)
       for (int i = 0; i < o; ++i) ck[a * o + i] = -(dh[(o + a) * N + i] - dh[i * N + o + a]);
     double* dck = c->alloc(nov);
-    hck(hipMemcpy(dck, ck.data(), nov * sizeof(double), hipMemcpyHostToDevice));
+    c->xfer(dck, ck.data(), nov * sizeof(double), hipMemcpyHostToDevice);
     c->axpby(1.0, dck, 1.0, rhs, nov);
   }
   c->axpby(0.0, rhs, -1.0, rhs, nov);
@@ -1170,6 +1188,11 @@ int guarded(scc_ctx* c, scc_info* info, F&& f) {
   double f0 = c ? c->flops : 0;
   int rc;
   try {
+    if (c) {
+      // order after the caller's stream
+      hck(hipEventRecord(c->entry_ev, c->user_s));
+      hck(hipStreamWaitEvent(c->s, c->entry_ev, 0));
+    }
     rc = f();
     if (c) {
       c->ex->flush_profile();
@@ -1203,6 +1226,7 @@ void default_opts(const scc_options* o, scc_options& out) {
   out.scc = 1;
   out.verbose = 0;
   out.precision = 0;
+  out.eager = 0;
   if (o) out = *o;
   if (out.tol_residual <= 0) out.tol_residual = 1e-10;
   if (out.tol_overlap <= 0) out.tol_overlap = 1e-11;
@@ -1264,7 +1288,9 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     Dims dd = c->m.d;
     c->sz = sizes_for(dd);
     default_opts(opts, c->opt);
-    c->s = (hipStream_t)hip_stream;
+    c->user_s = (hipStream_t)hip_stream;
+    hck(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking));
+    hck(hipEventCreateWithFlags(&c->entry_ev, hipEventDisableTiming));
     uintptr_t base = ((uintptr_t)workspace + 255) & ~(uintptr_t)255;
     c->arena = (double*)base;
     c->scratch = c->arena + p.arena;
@@ -1274,6 +1300,7 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     c->sz.pool = p.pool;
     c->ex = std::make_unique<Executor>(c->m.g, c->arena, c->scratch, c->scratch_n, c->partials);
     c->ex->plan_all();
+    c->ex->set_graphs(c->opt.eager == 0);
     c->D = c->alloc(c->sz.nvt);
     c->Dk = c->alloc(c->sz.nov);
     for (int k = 0; k < dd.ns; ++k) {
@@ -1297,8 +1324,8 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     std::vector<double> In((size_t)dd.n * dd.n, 0.0), Io((size_t)dd.o * dd.o, 0.0);
     for (int i = 0; i < dd.n; ++i) In[(size_t)i * dd.n + i] = 1.0;
     for (int i = 0; i < dd.o; ++i) Io[(size_t)i * dd.o + i] = 1.0;
-    hck(hipMemcpy(c->tp(m.In), In.data(), In.size() * sizeof(double), hipMemcpyHostToDevice));
-    hck(hipMemcpy(c->tp(m.Io), Io.data(), Io.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->xfer(c->tp(m.In), In.data(), In.size() * sizeof(double), hipMemcpyHostToDevice);
+    c->xfer(c->tp(m.Io), Io.data(), Io.size() * sizeof(double), hipMemcpyHostToDevice);
     c->set_scalar(m.one, 1.0);
     c->fill(c->tp(m.z2), m.g.t[m.z2].size(), 0.0);
     c->fill(c->tp(m.kappa), c->sz.nov, 0.0);
@@ -1351,7 +1378,7 @@ int scc_set_hamiltonian_fixed_basis(scc_ctx* c, const double* h, const double* c
     std::vector<double> ref((size_t)N * N, 0.0), C, F((size_t)N * N), w, V;
     if (orbitals_guess) {
       c->sync();
-      hck(hipMemcpy(ref.data(), orbitals_guess, ref.size() * sizeof(double), hipMemcpyDeviceToHost));
+      c->xfer(ref.data(), orbitals_guess, ref.size() * sizeof(double), hipMemcpyDeviceToHost);
     } else {
       for (int p = 0; p < N; ++p) ref[(size_t)p * N + p] = 1.0;
     }
@@ -1362,10 +1389,10 @@ int scc_set_hamiltonian_fixed_basis(scc_ctx* c, const double* h, const double* c
     int it = 0;
     double comm = 1.0;
     for (; it < 500; ++it) {
-      hck(hipMemcpyAsync(c->tp(m.Cmo), C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+      c->xfer(c->tp(m.Cmo), C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice);
       c->run(m.p_aofock);
       c->sync();
-      hck(hipMemcpy(F.data(), c->tp(m.Fao), F.size() * sizeof(double), hipMemcpyDeviceToHost));
+      c->xfer(F.data(), c->tp(m.Fao), F.size() * sizeof(double), hipMemcpyDeviceToHost);
       std::vector<double> D((size_t)N * N, 0.0);
       for (int p = 0; p < N; ++p)
         for (int q = 0; q < N; ++q) {
@@ -1393,8 +1420,8 @@ int scc_set_hamiltonian_fixed_basis(scc_ctx* c, const double* h, const double* c
     }
     if (comm >= tol) throw SccError(SCC_ENOCONV, "RHF iterations did not converge");
     c->log(" RHF converged in %d iterations (max |FD - DF| %.2e)\n", it, comm);
-    hck(hipMemcpyAsync(c->tp(m.Cmo), C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
-    if (orbitals) hck(hipMemcpyAsync(orbitals, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+    c->xfer(c->tp(m.Cmo), C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (orbitals) c->xfer(orbitals, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice);
     c->run(m.p_aotrans);
     c->cp(c->tp(m.h), c->tp(m.hmo), m.g.t[m.h].size());
     c->cp(c->tp(m.L), c->tp(m.Lmo), m.g.t[m.L].size());
@@ -1417,7 +1444,7 @@ int install_mo_hamiltonian_impl(scc_ctx* c, double e_nuc) {
     const int N = m.d.n, o = m.d.o, v = m.d.v;
     std::vector<double> F((size_t)N * N);
     c->sync();
-    hck(hipMemcpy(F.data(), c->tp(m.fock), F.size() * sizeof(double), hipMemcpyDeviceToHost));
+    c->xfer(F.data(), c->tp(m.fock), F.size() * sizeof(double), hipMemcpyDeviceToHost);
     c->eps.resize(N);
     for (int p = 0; p < N; ++p) c->eps[p] = F[(size_t)p * N + p];
     double fai = 0;
@@ -1432,7 +1459,7 @@ int install_mo_hamiltonian_impl(scc_ctx* c, double e_nuc) {
     // the closed-shell RHF Hessian, eps_a - eps_i + 3 (ai|ai) - (aa|ii).
     const int J = m.d.nj;
     std::vector<double> Lh((size_t)J * N * N);
-    hck(hipMemcpy(Lh.data(), c->tp(m.L), Lh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    c->xfer(Lh.data(), c->tp(m.L), Lh.size() * sizeof(double), hipMemcpyDeviceToHost);
     std::vector<double> D(c->sz.nvt), Dk(c->sz.nov);
     const int64_t nov = c->sz.nov;
     for (int a = 0; a < v; ++a)
@@ -1455,8 +1482,8 @@ int install_mo_hamiltonian_impl(scc_ctx* c, double e_nuc) {
         D[nov + p * nov + q] = c->eps[o + ap] - c->eps[ip] + c->eps[o + aq] - c->eps[iq];
       }
     }
-    hck(hipMemcpy(c->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
-    hck(hipMemcpy(c->Dk, Dk.data(), Dk.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->xfer(c->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice);
+    c->xfer(c->Dk, Dk.data(), Dk.size() * sizeof(double), hipMemcpyHostToDevice);
     // every geometry starts cold: t = 0 (the first Jacobi step is MP2), zeta = 0
     c->fill(c->tp(m.t1), nov, 0.0);
     c->fill(c->tp(m.t2), nov * nov, 0.0);
@@ -1477,16 +1504,45 @@ int scc_ground(scc_ctx* c, const double* guess_t, double* e0, scc_info* info) {
   }
   return guarded(c, info, [&]() -> int {
     Model& m = c->m;
-    if (guess_t) {
-      c->put(m.t1, guess_t);
-      c->put(m.t2, guess_t + c->sz.nov);
-    }
+    const int64_t nov = c->sz.nov, nvt = c->sz.nvt;
     for (int z : m.zeta) c->set_scalar(z, 0.0);
+    if (guess_t) {
+      // the residual judges the guess: it is used only if its residual is
+      // below that of the plain start (the MP2 amplitudes, the first step
+      // from t = 0)
+      int64_t mark = c->pool_used;
+      double* r = c->alloc(nvt);
+      double* tm = c->alloc(nvt);
+      auto resnorm = [&](const double* t) {
+        c->put(m.t1, t);
+        c->put(m.t2, t + nov);
+        c->run(m.p_res);
+        c->get(m.res.O1, r);
+        c->get(m.res.O2, r + nov);
+        c->sym_doubles(r + nov);
+        return std::sqrt(c->dot(r, r, nvt));
+      };
+      c->fill(tm, nvt, 0.0);
+      resnorm(tm);
+      launch_precond(r, c->D, 0.0, 1e-8, tm, nvt, c->s);
+      c->axpby(0.0, tm, -1.0, tm, nvt);
+      const double r_plain = resnorm(tm);
+      const double r_guess = resnorm(guess_t);
+      const bool use = std::isfinite(r_guess) && r_guess < r_plain;
+      c->log(" ground guess: residual %.3e (plain start %.3e) -> %s\n", r_guess, r_plain, use ? "used" : "rejected");
+      if (!use) {
+        c->put(m.t1, tm);
+        c->put(m.t2, tm + nov);
+        if (info) info->fallback_used = 1;
+      }
+      c->pool_used = mark;
+    }
     double rn = 0;
     int rc = ground_solve(c, c->opt.tol_residual, c->opt.max_iter, rn);
     c->E0 = c->tensor_scalar(m.res.E) + c->enuc;
     if (e0) launch_fill(e0, 1, c->E0, c->s);
     if (info) {
+      info->iterations = c->last_ground_its;
       info->residual = rn;
       info->converged = rc == SCC_OK;
     }
@@ -1506,9 +1562,37 @@ int scc_excited(scc_ctx* c, int nstates, const double* guess, double* energies, 
     c->err = "scc_excited before scc_set_hamiltonian";
     return SCC_ESTATE;
   }
-  (void)guess;
   return guarded(c, info, [&]() -> int {
-    int rc = excited_solve(c, info);
+    int rc = SCC_ENOCONV;
+    if (guess) {
+      // start from the given states and zeta; fall back to the plain start
+      // (CCSD states at zeta = 0) if that solve fails
+      const int ns = c->m.d.ns, np = c->m.d.npairs();
+      const int64_t nst = c->sz.nst;
+      for (int k = 0; k < ns; ++k) c->cp(c->R[k], guess + k * nst, nst);
+      std::vector<double> z(np, 0.0);
+      if (np) c->xfer(z.data(), guess + (int64_t)ns * nst, np * sizeof(double), hipMemcpyDeviceToHost);
+      bool finite = true;
+      for (double x : z) finite = finite && std::isfinite(x);
+      if (finite) {
+        c->zeta = z;
+        c->Jz.clear();
+        try {
+          int iters = 0;
+          rc = excited_pass(c, c->opt.tol_residual, c->opt.tol_overlap, true, iters);
+          if (info) info->iterations = iters;
+        } catch (const SccError& e) {
+          rc = e.code;
+        }
+      }
+      c->log(" excited-state guess %s\n", rc == SCC_OK ? "used" : "rejected");
+      if (rc != SCC_OK && info) info->fallback_used = 1;
+    }
+    if (rc != SCC_OK) {
+      int fb = info ? info->fallback_used : 0;
+      rc = excited_solve(c, info);
+      if (info) info->fallback_used = fb;
+    }
     if (rc) return rc;
     c->have_ground = c->have_excited = true;
     c->have_mult = false;
@@ -1517,9 +1601,9 @@ int scc_excited(scc_ctx* c, int nstates, const double* guess, double* energies, 
     if (energies) {
       std::vector<double> e(c->E);
       for (auto& x : e) x += c->enuc;
-      hck(hipMemcpy(energies, e.data(), e.size() * sizeof(double), hipMemcpyHostToDevice));
+      c->xfer(energies, e.data(), e.size() * sizeof(double), hipMemcpyHostToDevice);
     }
-    if (zeta && !c->zeta.empty()) hck(hipMemcpy(zeta, c->zeta.data(), c->zeta.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (zeta && !c->zeta.empty()) c->xfer(zeta, c->zeta.data(), c->zeta.size() * sizeof(double), hipMemcpyHostToDevice);
     return SCC_OK;
   });
 }

@@ -51,6 +51,10 @@ CONFIGS = {
     "o30v270": dict(o=30, v=270, nj=900, nstates=4, ncoord=90,
                     nacs=[(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)],
                     sf=0.01, sl=0.01),
+    # trajectory family H(x) = H0 + sum_k x_k H_k of the learned guess, at
+    # the o4v12 size with 36 coordinates and N(0, 0.01) perturbations
+    "o4v12x36": dict(o=4, v=12, nj=48, nstates=2, ncoord=36, nacs=[(0, 1)],
+                     sf=0.01, sl=0.01),
     # small ragged systems for parity tests (several GEMM tiles + tails)
     "o5v19": dict(o=5, v=19, nj=40, nstates=2, ncoord=3, nacs=[(0, 1)],
                   sf=0.002, sl=0.002),
@@ -66,7 +70,7 @@ CONFIGS = {
 }
 
 CONFIG_SEEDS = {"o4v12": 1001, "o10v90": 1002, "o20v180": 1003,
-                "o30v270": 1005}
+                "o4v12x36": 1004, "o30v270": 1005}
 
 
 @dataclass
@@ -181,3 +185,9 @@ def trajectory(ncoord, ngeom, seed):
     ph = rng.uniform(0, 2 * np.pi, size=ncoord)
     nn = np.arange(ngeom)[:, None]
     return A * np.sin(2 * np.pi * f * nn / 100.0 + ph)
+
+
+def family_geometries(ncoord, seeds, std=0.05):
+    """Geometries x ~ N(0, std^2) i.i.d. per coordinate, one seed each
+    (training seeds 10000.., held-out seeds 20000..)."""
+    return np.stack([np.random.Generator(np.random.PCG64(sd)).normal(0, std, size=ncoord) for sd in seeds])

@@ -12,8 +12,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "scc.h")).read()
-    return sorted(set(re.findall(r"\b(scc_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in ("scc.h", "scc_learn.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"\b(scc_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_and_binding_agree():

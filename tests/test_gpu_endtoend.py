@@ -231,3 +231,36 @@ def test_fixed_basis_displaced_geometry():
     d1, z3, kb = ctx.densities()
     d1_ref = ref[("nac", S.nacs[0][1], S.nacs[0][0])]["D1"]
     assert np.abs(d1.cpu().numpy() - d1_ref).max() < 1e-9 * max(1.0, np.abs(d1_ref).max())
+
+
+def test_graph_replays_match_eager_launches():
+    """Programs captured as HIP graphs and replayed many times (with other
+    programs and host synchronisations in between) give bitwise the results
+    of launching every kernel eagerly."""
+    from paper_2403_01007_amd import Context
+    from synth_inputs import random_amplitudes
+    S = make_system("o2v4")
+    print("[graphs vs eager o2v4]", flush=True)
+    h, L = S.at(np.zeros(S.ncoord))
+    t1, t2 = random_amplitudes(S.o, S.v, seed=5, scale=0.05)
+    t = np.concatenate([t1.ravel(), t2.ravel()])
+    r1, r2 = random_amplitudes(S.o, S.v, seed=6, scale=0.3)
+    vec = np.concatenate([[0.3], r1.ravel(), r2.ravel()])
+    outs = []
+    for eager in (True, False):
+        ctx = Context(S.o, S.v, S.nj, S.nstates, eager=eager)
+        ctx.set_hamiltonian(h, L)
+        reps = []
+        for _ in range(4):
+            reps.append(ctx.eval_residual(t).cpu().numpy())
+            reps.append(ctx.eval_sigma(vec).cpu().numpy())
+            reps.append(ctx.eval_left(vec).cpu().numpy())
+        outs.append(reps)
+        E, z, _ = ctx.excited()
+        outs[-1].append(E)
+        outs[-1].append(ctx.gradient(0, S.dh, S.dL)[0])
+        outs[-1].append(ctx.nac(0, 1, S.dh, S.dL)[0])
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    for k in range(3, 12):
+        assert np.array_equal(outs[1][k], outs[1][k % 3])
