@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no HIP graphs)")
     ap.add_argument("--no-roofline", action="store_true", help="no per-GEMM event timing in the timed region")
+    ap.add_argument("--one-target-at-a-time", action="store_true",
+                    help="solve the multiplier equations of each gradient / coupling separately")
     ap.add_argument("--learned", action="store_true",
                     help="learned initial guesses: train on the trajectory family, time held-out geometries")
     ap.add_argument("--learned-workload", default="o4v12x36")
@@ -182,14 +184,22 @@ def main():
         E, zeta, info = ctx.excited()
         phase("excited", info)
         out = {"E": E, "zeta": zeta}
+        if args.one_target_at_a_time:
+            for n in range(S.nstates):
+                g, info = ctx.gradient(n, dh, dL)
+                phase(f"gradient {n}", info)
+                out[f"g{n}"] = g
+            for (m, n) in S.nacs:
+                d, info = ctx.nac(m, n, dh, dL)
+                phase(f"coupling {m},{n}", info)
+                out[f"d{m}{n}"] = d
+            return out
+        g, d, info = ctx.gradients_and_couplings(list(range(S.nstates)), list(S.nacs), dh, dL)
+        phase(f"{S.nstates} gradients + {len(S.nacs)} couplings", info)
         for n in range(S.nstates):
-            g, info = ctx.gradient(n, dh, dL)
-            phase(f"gradient {n}", info)
-            out[f"g{n}"] = g
-        for (m, n) in S.nacs:
-            d, info = ctx.nac(m, n, dh, dL)
-            phase(f"coupling {m},{n}", info)
-            out[f"d{m}{n}"] = d
+            out[f"g{n}"] = g[n]
+        for i, (m, n) in enumerate(S.nacs):
+            out[f"d{m}{n}"] = d[i]
         return out
 
     reference = None

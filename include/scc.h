@@ -182,6 +182,17 @@ int scc_gradient(scc_ctx* ctx, int n, int ncoord, const double* dh, const double
 int scc_nac(scc_ctx* ctx, int m, int n, int ncoord, const double* dh, const double* dchol, double* nac,
             scc_info* info);
 
+/* Gradients of several states and couplings of several pairs in one call
+ * (same quantities as scc_gradient / scc_nac): the multiplier equations of
+ * up to nstates + npairs targets are solved in lockstep, so that one pass of
+ * the Lagrangian products (the transposed Jacobian of the constraints)
+ * serves all of them; each target keeps its own Krylov recurrence.
+ * states: host int[ngrad]; pairs: host int[2 * npair] as (m, n);
+ * grads: device double[ngrad][ncoord]; nacs: device double[npair][ncoord].
+ * With precision = 1 the targets are solved one at a time. */
+int scc_gradients_and_couplings(scc_ctx* ctx, int ngrad, const int* states, int npair, const int* pairs, int ncoord,
+                                const double* dh, const double* dchol, double* grads, double* nacs, scc_info* info);
+
 /* Export solution fields to device buffers:
  *   SCC_FIELD_T      [t1 | t2]
  *   SCC_FIELD_R      right vector k  [R0 | R1 | R2]

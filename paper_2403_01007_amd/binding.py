@@ -14,7 +14,7 @@ FIELD_T, FIELD_R, FIELD_L, FIELD_E0, FIELD_OMEGA = 0, 1, 2, 3, 4
 
 EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_last_error",
                     "scc_set_hamiltonian", "scc_set_hamiltonian_fixed_basis", "scc_ground", "scc_excited", "scc_multipliers",
-                    "scc_densities", "scc_gradient", "scc_nac", "scc_get", "scc_eval_residual",
+                    "scc_densities", "scc_gradient", "scc_nac", "scc_gradients_and_couplings", "scc_get", "scc_eval_residual",
                     "scc_eval_sigma", "scc_eval_left", "scc_profile",
                     "scc_mlp_param_count", "scc_mlp_workspace_bytes", "scc_mlp_forward", "scc_mlp_loss_grad",
                     "scc_mlp_train", "scc_pca_workspace_bytes", "scc_pca_fit", "scc_pca_expand"]
@@ -75,6 +75,7 @@ def load_library():
     lib.scc_gradient.argtypes = [P, I, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_nac.argtypes = [P, I, I, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_get.argtypes = [P, I, I, P]
+    lib.scc_gradients_and_couplings.argtypes = [P, I, P, I, P, I, P, P, P, P, ctypes.POINTER(Info)]
     lib.scc_eval_residual.argtypes = [P, P, P, P, P]
     lib.scc_eval_sigma.argtypes = [P, P, P]
     lib.scc_eval_left.argtypes = [P, P, P]
@@ -228,6 +229,22 @@ class Context:
         self._check(self.lib.scc_nac(self.h, m, n, dh.shape[0], _ptr(dh), _ptr(dl), _ptr(out),
                                      ctypes.byref(info)), "scc_nac")
         return out.cpu().numpy(), info
+
+    def gradients_and_couplings(self, states, pairs, dh, dchol):
+        """All requested gradients and couplings in one call; returns (grads, nacs) host arrays."""
+        dh, dl = self._dev(dh), self._dev(dchol)
+        nc = dh.shape[0]
+        st = (ctypes.c_int * max(1, len(states)))(*states)
+        flat = [x for p in pairs for x in p]
+        pr = (ctypes.c_int * max(1, len(flat)))(*flat)
+        g = self.zeros(max(1, len(states)), nc)
+        d = self.zeros(max(1, len(pairs)), nc)
+        info = Info()
+        self._check(self.lib.scc_gradients_and_couplings(self.h, len(states), ctypes.cast(st, ctypes.c_void_p),
+                                                         len(pairs), ctypes.cast(pr, ctypes.c_void_p), nc, _ptr(dh),
+                                                         _ptr(dl), _ptr(g), _ptr(d), ctypes.byref(info)),
+                    "scc_gradients_and_couplings")
+        return g.cpu().numpy()[:len(states)], d.cpu().numpy()[:len(pairs)], info
 
     def get(self, field, k=0):
         nvt = self.nov + self.nov * self.nov

@@ -237,9 +237,10 @@ std::set<int> outputs_of(const Graph& g, const std::vector<int>& list) {
 
 }  // namespace
 
-void build_model(Model& m, const Dims& d, int nb) {
+void build_model(Model& m, const Dims& d, int nb, int nbt) {
   m.d = d;
   m.nb = nb;
+  m.nbt = nbt;
   Graph& g = m.g;
   const int64_t o = d.o, v = d.v, n = d.n, J = d.nj;
   const int ns = d.ns, np = d.npairs();
@@ -397,6 +398,16 @@ void build_model(Model& m, const Dims& d, int nb) {
     auto all = g.needed_ops(outs, have);
     m.p_lag = g.dependent_ops(all, mult_in);
     m.p_lag_pre = minus(all, m.p_lag);
+    if (nbt > 1) {
+      std::vector<int> ins;
+      for (int x : mult_in)
+        if (x != m.mF) ins.push_back(x);
+      std::map<int, int> mp;
+      m.p_lagB = g.batchify(m.p_lag, ins, nbt, mp);
+      for (int x : ins) m.lagB[x] = mp.at(x);
+      for (int x : outs)
+        if (mp.count(x)) m.lagB[x] = mp.at(x);
+    }
   }
   // orbital-rotation and integral adjoints (kappa-bar enters through F_ai)
   {
@@ -492,6 +503,7 @@ std::vector<int> host_tensors(const Model& m) {
   for (auto& s : m.mk) sg(s);
   for (const StateT* s : {&m.vin, &m.lin, &m.lout, &m.oa, &m.ob, &m.nac_l, &m.vinB, &m.sigB, &m.linB, &m.loutB})
     st(*s);
+  for (auto& kv : m.lagB) r.push_back(kv.second);
   return r;
 }
 
@@ -499,7 +511,7 @@ std::vector<const std::vector<int>*> programs(const Model& m) {
   std::vector<const std::vector<int>*> r = {&m.p_setup, &m.p_res,      &m.p_sig_pre, &m.p_sig,   &m.p_left,
                                             &m.p_ovl,   &m.p_dens,     &m.p_lag_pre, &m.p_lag,   &m.p_kappa,
                                             &m.p_fk,    &m.p_integral, &m.p_sigB,    &m.p_leftB,
-                                            &m.p_aofock, &m.p_aotrans, &m.p_aodens};
+                                            &m.p_aofock, &m.p_aotrans, &m.p_aodens, &m.p_lagB};
   for (auto& p : m.p_nac) r.push_back(&p);
   return r;
 }

@@ -1,5 +1,6 @@
 // Construction of the SCCSD(E) programs on a contraction graph.
 #pragma once
+#include <map>
 #include <vector>
 
 #include "ir.hpp"
@@ -98,13 +99,19 @@ struct Model {
   int nb = 1;
   StateT vinB{}, sigB{}, linB{}, loutB{};
   std::vector<int> p_sigB, p_leftB;
+  // --- Lagrangian products J^T lambda-bar for nbt targets at once: batched
+  //     copy of p_lag; lagB maps each multiplier input and adjoint output to
+  //     its batched tensor [nbt, ...]
+  int nbt = 1;
+  std::map<int, int> lagB;
+  std::vector<int> p_lagB;
 
   // op lists
   std::vector<int> p_setup, p_res, p_sig_pre, p_sig, p_left, p_ovl, p_dens, p_lag_pre, p_lag, p_kappa, p_fk,
       p_integral;
 };
 
-void build_model(Model& m, const Dims& d, int nb = 1);
+void build_model(Model& m, const Dims& d, int nb = 1, int nbt = 1);
 
 // Every op list the context runs (the storage plan relies on this list).
 std::vector<const std::vector<int>*> programs(const Model& m);

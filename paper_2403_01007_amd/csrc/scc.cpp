@@ -47,6 +47,8 @@ int64_t up(int64_t x, int64_t a = 32) { return (x + a - 1) / a * a; }
 struct Sizes {
   int64_t nov, nvt, nst, nlag;
   int maxsub, cap_lag, cap_k;
+  int nbt, cap_b;        // targets per batched multiplier solve, Krylov capacity of each
+  int64_t krylov;        // doubles of the Krylov region (single or batched solves)
   int64_t pool;
 };
 
@@ -63,9 +65,17 @@ Sizes sizes_for(const Dims& d) {
   p += 2 * NDIIS * up(s.nvt) + 3 * up(s.nvt);
   p += 2 * s.maxsub * up(s.nvt) + 6 * (d.ns + 2) * up(s.nvt) + 2 * up(s.nvt);
   // recycled GCR spaces: Lagrangian (budget 32 GB) and orbital response
-  s.cap_lag = (int)std::max<int64_t>(20, std::min<int64_t>(400, (int64_t)(32e9 / (16.0 * up(s.nlag)))));
+  // Krylov spaces of the multiplier solves share one region (96 GB budget):
+  // one target with up to 400 directions, or nbt targets in lockstep
+  const double budget = 96e9;
+  s.cap_lag = (int)std::max<int64_t>(20, std::min<int64_t>(400, (int64_t)(budget / (16.0 * up(s.nlag)))));
+  s.nbt = std::max(1, d.ns + d.npairs());
+  s.cap_b = (int)std::max<int64_t>(20, std::min<int64_t>(400, (int64_t)(budget / (16.0 * up(s.nlag) * s.nbt))));
+  s.krylov = std::max<int64_t>(2 * (int64_t)s.cap_lag * up(s.nlag), 2 * (int64_t)s.nbt * s.cap_b * up(s.nlag));
+  // per-target vectors of the batched solve: b, x, r, z, w
+  p += 5 * (int64_t)s.nbt * up(s.nlag) + (int64_t)s.nbt * up(s.cap_b);
   s.cap_k = 300;
-  p += 2 * (int64_t)s.cap_lag * up(s.nlag) + up(s.cap_lag) + 4 * up(s.nlag);
+  p += s.krylov + up(s.cap_lag) + 4 * up(s.nlag);
   p += 2 * (int64_t)s.cap_k * up(s.nov) + up(s.cap_k) + 4 * up(s.nov);
   p += 64;
   s.pool = p;
@@ -120,6 +130,9 @@ struct scc_ctx {
   std::vector<double> Jz;     // zeta Jacobian dO/dzeta of the last SCC solve
   bool fixed_basis = false;   // Hamiltonian (and derivative integrals) in a fixed basis
   int last_ground_its = 0;    // iterations of the last ground-state solve
+  double* krylov = nullptr;   // Krylov region of the multiplier solves
+  double* batch_coef = nullptr;
+  double* batch_vec = nullptr;
   double E0 = 0.0, enuc = 0.0;
   std::vector<double> E, zeta;
   int mult_kind = -1, mult_m = -1, mult_n = -1;
@@ -1028,24 +1041,12 @@ void set_lagrangian_point(scc_ctx* c) {
   c->run(m.p_lag_pre);
 }
 
-int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
+// right-hand side b = -dTarget/dlambda (parameter layout) of the gradient of
+// E_n (kind 0) or the coupling target O_mn (kind 1)
+void lag_rhs(scc_ctx* c, const std::vector<int64_t>& offs, int kind, int mm, int nn, double* b) {
   Model& m = c->m;
-  const int ns = m.d.ns;
-  const int64_t nov = c->sz.nov, n = c->sz.nlag;
-  set_lagrangian_point(c);
-  auto segs = lag_segments(c);
-  int64_t mark = c->pool_used;
-  double* b = c->alloc(n);
-  double* x = c->alloc(n);
+  const int64_t n = c->sz.nlag;
   c->fill(b, n, 0.0);
-  c->fill(x, n, 0.0);
-  // right-hand side b = -dTarget/dlambda (parameter layout)
-  int64_t off = 0;
-  std::vector<int64_t> offs;
-  for (auto& sg : segs) {
-    offs.push_back(off);
-    off += sg.n;
-  }
   if (kind == 0) {
     // gradient of E_n: unit vector on the E_n parameter
     int idx = 2 + 4 * nn + 3;
@@ -1061,25 +1062,102 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
     c->get(m.a_nac_r[nn].r2, b + offs[base + 2]);
     c->axpby(0.0, b, -1.0, b, n);
   }
-  // preconditioner: orbital-energy differences on the amplitude blocks
+}
+
+// block-diagonal preconditioner: orbital-energy differences (shifted by
+// omega_k on the state blocks) on the amplitude blocks, identity elsewhere
+void lag_prec(scc_ctx* c, const std::vector<Seg>& segs, const std::vector<int64_t>& offs, const double* in,
+              double* out) {
+  const int64_t nov = c->sz.nov;
   double* dzero = c->dsc + 8;
   c->fill(dzero, 1, 0.0);
-  auto prec = [&](const double* in, double* out) {
-    for (size_t i = 0; i < segs.size(); ++i) {
-      const Seg& sg = segs[i];
-      if (!sg.active) {
-        c->fill(out + offs[i], sg.n, 0.0);
-        continue;
-      }
-      if (sg.kind < 0) {
-        c->cp(out + offs[i], in + offs[i], sg.n);
-        continue;
-      }
-      double shift = sg.kind == 0 ? 0.0 : (c->E[sg.kind - 1] - c->E0);
-      const double* Dseg = sg.comp == 0 ? dzero : (sg.comp == 1 ? c->D : c->D + nov);
-      launch_precond(in + offs[i], Dseg, shift, 0.05, out + offs[i], sg.n, c->s);
+  for (size_t i = 0; i < segs.size(); ++i) {
+    const Seg& sg = segs[i];
+    if (!sg.active) {
+      c->fill(out + offs[i], sg.n, 0.0);
+      continue;
     }
+    if (sg.kind < 0) {
+      c->cp(out + offs[i], in + offs[i], sg.n);
+      continue;
+    }
+    double shift = sg.kind == 0 ? 0.0 : (c->E[sg.kind - 1] - c->E0);
+    const double* Dseg = sg.comp == 0 ? dzero : (sg.comp == 1 ? c->D : c->D + nov);
+    launch_precond(in + offs[i], Dseg, shift, 0.05, out + offs[i], sg.n, c->s);
+  }
+}
+
+// with the multipliers x of one target: orbital multipliers
+// A_HF^T kbar = -(eta_kappa + dTarget/dkappa); leaves the multipliers in
+// their tensors and kbar in c->kbar
+int orbital_response(scc_ctx* c, const std::vector<Seg>& segs, const std::vector<int64_t>& offs, const double* x,
+                     int kind, int mm, int nn, int& itk, double& relk) {
+  Model& m = c->m;
+  const int64_t nov = c->sz.nov;
+  for (size_t i = 0; i < segs.size(); ++i) {
+    if (segs[i].active)
+      c->put(segs[i].mult, x + offs[i]);
+    else
+      c->fill(c->tp(segs[i].mult), segs[i].n, 0.0);
+  }
+  int64_t mark = c->pool_used;
+  c->fill(c->tp(m.mF), nov, 0.0);
+  c->run(m.p_kappa);
+  double* rhs = c->alloc(nov);
+  c->get(m.a_kappa, rhs);
+  if (kind == 1) {
+    // coupling: dO_mn/dkappa_ai = -(d_ai - d_ia) with d = d(calL_m, calR_n)
+    c->run(m.p_sig_pre);
+    c->put_state(m.vin, c->R[nn]);
+    c->put_state(m.lin, c->Lv[mm]);
+    c->run(m.p_dens);
+    std::vector<double> dh((size_t)m.d.n * m.d.n, 0.0);
+    if (!c->zero(m.dens_hk)) c->xfer(dh.data(), c->tp(m.dens_hk), dh.size() * sizeof(double), hipMemcpyDeviceToHost);
+    std::vector<double> ck(nov);
+    const int o = m.d.o, v = m.d.v, N = m.d.n;
+    for (int a = 0; a < v; ++a)
+      for (int i = 0; i < o; ++i) ck[a * o + i] = -(dh[(o + a) * N + i] - dh[i * N + o + a]);
+    double* dck = c->alloc(nov);
+    c->xfer(dck, ck.data(), nov * sizeof(double), hipMemcpyHostToDevice);
+    c->axpby(1.0, dck, 1.0, rhs, nov);
+  }
+  c->axpby(0.0, rhs, -1.0, rhs, nov);
+  auto applyF = [&](const double* in, double* out) {
+    c->put(m.mF, in);
+    c->run(m.p_fk);
+    c->get(m.fk_adj, out);
   };
+  auto precF = [&](const double* in, double* out) { launch_precond(in, c->Dk, 0.0, 1e-3, out, nov, c->s); };
+  c->fill(c->kbar, nov, 0.0);
+  int rc = gcr(c, c->rec_k, applyF, precF, rhs, c->kbar, c->opt.tol_residual, std::max(c->opt.max_iter, c->rec_k.cap),
+               itk, relk);
+  c->put(m.mF, c->kbar);
+  c->pool_used = mark;
+  if (rc) return rc;
+  c->have_mult = true;
+  c->mult_kind = kind;
+  c->mult_m = mm;
+  c->mult_n = nn;
+  return SCC_OK;
+}
+
+int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
+  Model& m = c->m;
+  const int64_t n = c->sz.nlag;
+  set_lagrangian_point(c);
+  auto segs = lag_segments(c);
+  int64_t mark = c->pool_used;
+  double* b = c->alloc(n);
+  double* x = c->alloc(n);
+  c->fill(x, n, 0.0);
+  int64_t off = 0;
+  std::vector<int64_t> offs;
+  for (auto& sg : segs) {
+    offs.push_back(off);
+    off += sg.n;
+  }
+  lag_rhs(c, offs, kind, mm, nn, b);
+  auto prec = [&](const double* in, double* out) { lag_prec(c, segs, offs, in, out); };
   auto apply = [&](const double* in, double* out) {
     for (size_t i = 0; i < segs.size(); ++i) {
       if (segs[i].active)
@@ -1118,67 +1196,236 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
     c->pool_used = mark;
     return rc;
   }
-  // leave the multipliers in their tensors
-  for (size_t i = 0; i < segs.size(); ++i) {
-    if (segs[i].active)
-      c->put(segs[i].mult, x + offs[i]);
-    else
-      c->fill(c->tp(segs[i].mult), segs[i].n, 0.0);
-  }
-  // orbital multipliers: A_HF^T kbar = -(eta_kappa + dTarget/dkappa)
-  c->fill(c->tp(m.mF), nov, 0.0);
-  c->run(m.p_kappa);
-  double* rhs = c->alloc(nov);
-  c->get(m.a_kappa, rhs);
-  if (kind == 1) {
-    // coupling: dO_mn/dkappa_ai = -(d_ai - d_ia) with d = d(calL_m, calR_n)
-    c->run(m.p_sig_pre);
-    c->put_state(m.vin, c->R[nn]);
-    c->put_state(m.lin, c->Lv[mm]);
-    c->run(m.p_dens);
-    std::vector<double> dh((size_t)m.d.n * m.d.n);
-    c->sync();
-    if (!c->zero(m.dens_hk)) c->xfer(dh.data(), c->tp(m.dens_hk), dh.size() * sizeof(double), hipMemcpyDeviceToHost);
-    std::vector<double> ck(nov);
-    const int o = m.d.o, v = m.d.v, N = m.d.n;
-    for (int a = 0; a < v; ++a)
-      for (int i = 0; i < o; ++i) ck[a * o + i] = -(dh[(o + a) * N + i] - dh[i * N + o + a]);
-    double* dck = c->alloc(nov);
-    c->xfer(dck, ck.data(), nov * sizeof(double), hipMemcpyHostToDevice);
-    c->axpby(1.0, dck, 1.0, rhs, nov);
-  }
-  c->axpby(0.0, rhs, -1.0, rhs, nov);
-  auto applyF = [&](const double* in, double* out) {
-    c->put(m.mF, in);
-    c->run(m.p_fk);
-    c->get(m.fk_adj, out);
-  };
-  auto precF = [&](const double* in, double* out) { launch_precond(in, c->Dk, 0.0, 1e-3, out, nov, c->s); };
-  c->fill(c->kbar, nov, 0.0);
   int itk = 0;
   double relk = 0;
-  rc = gcr(c, c->rec_k, applyF, precF, rhs, c->kbar, c->opt.tol_residual, std::max(c->opt.max_iter, c->rec_k.cap),
-           itk, relk);
-  c->put(m.mF, c->kbar);
+  rc = orbital_response(c, segs, offs, x, kind, mm, nn, itk, relk);
   c->pool_used = mark;
   if (rc) return rc;
-  c->have_mult = true;
-  c->mult_kind = kind;
-  c->mult_m = mm;
-  c->mult_n = nn;
   if (info) {
     info->iterations = iters + itk;
     info->residual = std::max(rel, relk);
     info->converged = 1;
   }
-  (void)ns;
   return SCC_OK;
 }
+
 
 int integral_adjoints(scc_ctx* c) {
   Model& m = c->m;
   c->put(m.mF, c->kbar);
   c->run(m.p_integral);
+  return SCC_OK;
+}
+
+// Effective densities of the current multipliers contracted with the
+// derivative integrals: out[k] = <dh_k, D1> + <dL_k, Z>
+void contract_derivatives(scc_ctx* c, int ncoord, const double* dh, const double* dchol, double* out) {
+  integral_adjoints(c);
+  const int64_t N = c->m.d.n, J = c->m.d.nj;
+  int d1id = c->m.a_h, zid = c->m.a_L;
+  if (c->fixed_basis) {
+    // derivative integrals in the fixed basis: densities C D1 C^T, C Z C^T
+    c->run(c->m.p_aodens);
+    d1id = c->m.d1ao;
+    zid = c->m.zao;
+  }
+  double* D1 = c->zero(d1id) ? nullptr : c->tp(d1id);
+  double* Z = c->zero(zid) ? nullptr : c->tp(zid);
+  if (!D1 || !Z) throw SccError(SCC_EDEVICE, "empty density");
+  launch_deriv_contract(dh, N * N, D1, dchol, J * N * N, Z, ncoord, out, c->partials, c->s);
+}
+
+struct Target {
+  int kind, m, n;
+  double* out;
+};
+
+// Multiplier equations of several targets solved in lockstep: one pass of
+// the batched Lagrangian products (p_lagB) serves up to nbt targets per
+// Krylov step; each target keeps its own GCR/ORTHODIR recurrence (the same
+// steps as gcr() above).  Then orbital response and derivative contraction
+// per target.  Targets that do not converge within the batched capacity are
+// solved alone.
+int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const double* dh, const double* dchol,
+                  int& iters_total) {
+  Model& m = c->m;
+  const int64_t n = c->sz.nlag, un = up(c->sz.nlag);
+  const int nbt = c->sz.nbt, cap = c->sz.cap_b;
+  const double tol = c->opt.tol_residual;
+  set_lagrangian_point(c);
+  auto segs = lag_segments(c);
+  std::vector<int64_t> offs;
+  {
+    int64_t off = 0;
+    for (auto& sg : segs) {
+      offs.push_back(off);
+      off += sg.n;
+    }
+  }
+  auto prec = [&](const double* in, double* out) { lag_prec(c, segs, offs, in, out); };
+  // out_j = J^T in_j for the listed slots (at most nbt), other slots zero
+  auto applyB = [&](const std::vector<const double*>& in, const std::vector<double*>& out) {
+    for (size_t i = 0; i < segs.size(); ++i) {
+      const Seg& sg = segs[i];
+      double* base = c->tp(m.lagB.at(sg.mult));
+      for (int j = 0; j < nbt; ++j) {
+        if (j < (int)in.size() && in[j] && sg.active)
+          c->cp(base + (int64_t)j * sg.n, in[j] + offs[i], sg.n);
+        else
+          c->fill(base + (int64_t)j * sg.n, sg.n, 0.0);
+      }
+    }
+    c->run(m.p_lagB);
+    for (size_t i = 0; i < segs.size(); ++i) {
+      const Seg& sg = segs[i];
+      auto it = m.lagB.find(sg.adj);
+      for (int j = 0; j < (int)out.size(); ++j) {
+        if (!out[j]) continue;
+        if (!sg.active || it == m.lagB.end()) {
+          c->fill(out[j] + offs[i], sg.n, 0.0);
+          continue;
+        }
+        c->cp(out[j] + offs[i], c->tp(it->second) + (int64_t)j * sg.n, sg.n);
+        if (sg.comp == 2) c->sym_doubles(out[j] + offs[i]);
+      }
+    }
+  };
+  const int maxg = std::max(c->opt.max_iter, cap);
+  std::vector<int> failed;
+  for (size_t b0 = 0; b0 < tg.size(); b0 += nbt) {
+    const int nb = (int)std::min<size_t>(nbt, tg.size() - b0);
+    std::vector<double*> B(nb), X(nb), R(nb), Z(nb), W(nb), U(nb), C(nb), cf(nb);
+    std::vector<int> k(nb, 0), done(nb, 0), checks(nb, 0);
+    std::vector<char> first(nb, 1), reseed(nb, 0), force(nb, 0);
+    std::vector<double> bn(nb);
+    for (int j = 0; j < nb; ++j) {
+      B[j] = c->batch_vec + (0 * (int64_t)nbt + j) * un;
+      X[j] = c->batch_vec + (1 * (int64_t)nbt + j) * un;
+      R[j] = c->batch_vec + (2 * (int64_t)nbt + j) * un;
+      Z[j] = c->batch_vec + (3 * (int64_t)nbt + j) * un;
+      W[j] = c->batch_vec + (4 * (int64_t)nbt + j) * un;
+      U[j] = c->krylov + (2 * (int64_t)j) * cap * un;
+      C[j] = c->krylov + (2 * (int64_t)j + 1) * cap * un;
+      cf[j] = c->batch_coef + (int64_t)j * up(cap);
+      const Target& t = tg[b0 + j];
+      lag_rhs(c, offs, t.kind, t.m, t.n, B[j]);
+      c->fill(X[j], n, 0.0);
+      c->cp(R[j], B[j], n);
+      bn[j] = std::sqrt(c->dot(B[j], B[j], n));
+      if (bn[j] == 0) done[j] = 1;
+    }
+    int it = 0;
+    for (; it < maxg; ++it) {
+      // convergence, confirmed on the true residual b - A x
+      std::vector<const double*> cin(nb, nullptr);
+      std::vector<double*> cout(nb, nullptr);
+      bool any = false;
+      for (int j = 0; j < nb; ++j) {
+        if (done[j]) continue;
+        const double rel = force[j] ? 0.0 : std::sqrt(c->dot(R[j], R[j], n)) / bn[j];
+        if (it % 10 == 0) c->log("  batched gcr it %3d target %d (stored %d)  rel. residual %.3e\n", it, j, k[j], rel);
+        if (rel < tol) {
+          cin[j] = X[j];
+          cout[j] = W[j];
+          any = true;
+        }
+        force[j] = 0;
+      }
+      if (any) {
+        applyB(cin, cout);
+        for (int j = 0; j < nb; ++j) {
+          if (!cin[j]) continue;
+          c->cp(R[j], B[j], n);
+          c->axpby(-1.0, W[j], 1.0, R[j], n);
+          const double tr = std::sqrt(c->dot(R[j], R[j], n)) / bn[j];
+          c->log("  batched gcr it %3d target %d  true rel. residual %.3e\n", it, j, tr);
+          if (tr < 10 * tol)
+            done[j] = 1;
+          else if (++checks[j] > 3)
+            done[j] = -1;
+          else
+            reseed[j] = 1;
+        }
+      }
+      std::vector<const double*> zin(nb, nullptr);
+      std::vector<double*> wout(nb, nullptr);
+      bool running = false;
+      for (int j = 0; j < nb; ++j) {
+        if (done[j]) continue;
+        if (k[j] >= cap) {
+          done[j] = -1;
+          continue;
+        }
+        running = true;
+        const double* dir = (first[j] || reseed[j] || k[j] == 0) ? R[j] : C[j] + (int64_t)(k[j] - 1) * n;
+        prec(dir, Z[j]);
+        zin[j] = Z[j];
+        wout[j] = W[j];
+      }
+      if (!running) break;
+      applyB(zin, wout);
+      for (int j = 0; j < nb; ++j) {
+        if (!zin[j]) continue;
+        first[j] = 0;
+        const double w0 = std::sqrt(c->dot(W[j], W[j], n));
+        for (int pass = 0; pass < 2; ++pass) {
+          auto be = multi_dot(c, C[j], k[j], n, W[j]);
+          for (auto& v : be) v = -v;
+          multi_axpy(c, C[j], k[j], n, be, cf[j], W[j]);
+          multi_axpy(c, U[j], k[j], n, be, cf[j], Z[j]);
+        }
+        const double wn = std::sqrt(c->dot(W[j], W[j], n));
+        if (!(wn > 1e-12 * w0)) {
+          force[j] = 1;  // invariant space: confirm on the true residual
+          continue;
+        }
+        double* un_ = U[j] + (int64_t)k[j] * n;
+        double* cn_ = C[j] + (int64_t)k[j] * n;
+        c->cp(un_, Z[j], n);
+        c->axpby(0.0, Z[j], 1.0 / wn, un_, n);
+        c->cp(cn_, W[j], n);
+        c->axpby(0.0, W[j], 1.0 / wn, cn_, n);
+        ++k[j];
+        if (reseed[j]) {
+          // project the true residual on the whole stored space
+          auto al = multi_dot(c, C[j], k[j], n, R[j]);
+          multi_axpy(c, U[j], k[j], n, al, cf[j], X[j]);
+          for (auto& v : al) v = -v;
+          multi_axpy(c, C[j], k[j], n, al, cf[j], R[j]);
+          reseed[j] = 0;
+        } else {
+          const double al = c->dot(cn_, R[j], n);
+          c->axpby(al, un_, 1.0, X[j], n);
+          c->axpby(-al, cn_, 1.0, R[j], n);
+        }
+      }
+    }
+    iters_total += it;
+    // orbital response and contraction, target by target
+    for (int j = 0; j < nb; ++j) {
+      const Target& t = tg[b0 + j];
+      if (done[j] != 1) {
+        failed.push_back((int)(b0 + j));
+        continue;
+      }
+      int itk = 0;
+      double relk = 0;
+      int rc = orbital_response(c, segs, offs, X[j], t.kind, t.m, t.n, itk, relk);
+      if (rc) return rc;
+      iters_total += itk;
+      contract_derivatives(c, ncoord, dh, dchol, t.out);
+    }
+  }
+  // targets beyond the batched capacity: alone, with the full Krylov region
+  for (int f : failed) {
+    const Target& t = tg[f];
+    c->log("  target %d solved alone\n", f);
+    scc_info inf{};
+    int rc = multipliers_solve(c, t.kind, t.m, t.n, &inf);
+    if (rc) return rc;
+    iters_total += inf.iterations;
+    contract_derivatives(c, ncoord, dh, dchol, t.out);
+  }
   return SCC_OK;
 }
 
@@ -1243,7 +1490,7 @@ Plan make_plan(const scc_dims* d) {
   Plan p;
   p.m = std::make_unique<Model>();
   Dims dd{d->nocc, d->nvirt, d->nocc + d->nvirt, d->nchol, d->nstates};
-  build_model(*p.m, dd, dd.ns + 2);
+  build_model(*p.m, dd, dd.ns + 2, dd.ns + dd.npairs());
   p.arena = up(p.m->g.finalize(programs(*p.m), host_tensors(*p.m)), 32);
   p.scratch = up(std::max<int64_t>(Executor::plan_scratch(p.m->g), 32));
   p.pool = up(sizes_for(dd).pool);
@@ -1311,9 +1558,12 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     c->dsc = c->alloc(32);
     c->rec_lag.n = c->sz.nlag;
     c->rec_lag.cap = c->sz.cap_lag;
-    c->rec_lag.U = c->alloc((int64_t)c->sz.cap_lag * up(c->sz.nlag));
-    c->rec_lag.C = c->alloc((int64_t)c->sz.cap_lag * up(c->sz.nlag));
+    c->krylov = c->alloc(c->sz.krylov);
+    c->rec_lag.U = c->krylov;
+    c->rec_lag.C = c->krylov + (int64_t)c->sz.cap_lag * up(c->sz.nlag);
     c->rec_lag.coef = c->alloc(c->sz.cap_lag);
+    c->batch_coef = c->alloc((int64_t)c->sz.nbt * up(c->sz.cap_b));
+    c->batch_vec = c->alloc(5 * (int64_t)c->sz.nbt * up(c->sz.nlag));
     c->rec_k.n = c->sz.nov;
     c->rec_k.cap = c->sz.cap_k;
     c->rec_k.U = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
@@ -1661,19 +1911,7 @@ static int derivative(scc_ctx* c, int kind, int mm, int nn, int ncoord, const do
       int rc = multipliers_solve(c, kind, mm, nn, info);
       if (rc) return rc;
     }
-    integral_adjoints(c);
-    const int64_t N = c->m.d.n, J = c->m.d.nj;
-    int d1id = c->m.a_h, zid = c->m.a_L;
-    if (c->fixed_basis) {
-      // derivative integrals in the fixed basis: densities C D1 C^T, C Z C^T
-      c->run(c->m.p_aodens);
-      d1id = c->m.d1ao;
-      zid = c->m.zao;
-    }
-    double* D1 = c->zero(d1id) ? nullptr : c->tp(d1id);
-    double* Z = c->zero(zid) ? nullptr : c->tp(zid);
-    if (!D1 || !Z) throw SccError(SCC_EDEVICE, "empty density");
-    launch_deriv_contract(dh, N * N, D1, dchol, J * N * N, Z, ncoord, out, c->partials, c->s);
+    contract_derivatives(c, ncoord, dh, dchol, out);
     return SCC_OK;
   });
 }
@@ -1686,6 +1924,57 @@ int scc_gradient(scc_ctx* c, int n, int ncoord, const double* dh, const double* 
 int scc_nac(scc_ctx* c, int m, int n, int ncoord, const double* dh, const double* dchol, double* nac, scc_info* info) {
   if (c && (n < 0 || n >= c->m.d.ns || m < 0 || m >= c->m.d.ns || m == n)) return SCC_EINVAL;
   return derivative(c, 1, m, n, ncoord, dh, dchol, nac, info);
+}
+
+int scc_gradients_and_couplings(scc_ctx* c, int ngrad, const int* states, int npair, const int* pairs, int ncoord,
+                                const double* dh, const double* dchol, double* grads, double* nacs, scc_info* info) {
+  if (!c) return SCC_EINVAL;
+  const int ns = c->m.d.ns;
+  if (ngrad < 0 || npair < 0 || (ngrad > 0 && (!states || !grads)) || (npair > 0 && (!pairs || !nacs)) || !dh ||
+      !dchol || ncoord < 0 || (int64_t)ncoord * 256 > PARTIALS) {
+    c->err = "bad arguments";
+    return SCC_EINVAL;
+  }
+  std::vector<Target> tg;
+  for (int i = 0; i < ngrad; ++i) {
+    if (states[i] < 0 || states[i] >= ns) {
+      c->err = "bad state index";
+      return SCC_EINVAL;
+    }
+    tg.push_back({0, -1, states[i], grads + (int64_t)i * ncoord});
+  }
+  for (int i = 0; i < npair; ++i) {
+    const int mm = pairs[2 * i], nn = pairs[2 * i + 1];
+    if (mm < 0 || mm >= ns || nn < 0 || nn >= ns || mm == nn) {
+      c->err = "bad state pair";
+      return SCC_EINVAL;
+    }
+    tg.push_back({1, mm, nn, nacs + (int64_t)i * ncoord});
+  }
+  if (!c->have_excited) {
+    c->err = "gradients or couplings before scc_excited";
+    return SCC_ESTATE;
+  }
+  return guarded(c, info, [&]() -> int {
+    int iters = 0;
+    int rc = c->m.nbt > 1 && c->opt.precision == 0 ? targets_solve(c, tg, ncoord, dh, dchol, iters) : SCC_EINVAL;
+    if (c->m.nbt <= 1 || c->opt.precision != 0) {
+      // one target at a time (reduced-precision mode refines each in FP64)
+      rc = SCC_OK;
+      for (auto& t : tg) {
+        scc_info inf{};
+        rc = multipliers_solve(c, t.kind, t.m, t.n, &inf);
+        if (rc) break;
+        iters += inf.iterations;
+        contract_derivatives(c, ncoord, dh, dchol, t.out);
+      }
+    }
+    if (info) {
+      info->iterations = iters;
+      info->converged = rc == SCC_OK;
+    }
+    return rc;
+  });
 }
 
 int scc_get(scc_ctx* c, int field, int k, double* out) {

@@ -264,3 +264,17 @@ def test_graph_replays_match_eager_launches():
         assert np.array_equal(a, b)
     for k in range(3, 12):
         assert np.array_equal(outs[1][k], outs[1][k % 3])
+
+
+def test_batched_targets_match_single_target_solves():
+    """scc_gradients_and_couplings (all targets in lockstep) reproduces the
+    one-target-at-a-time results."""
+    S = make_system("o5v19", seed=7)
+    print("[batched targets o5v19]", flush=True)
+    ctx, e0, E, z, grads, nacs = _run_gpu(S)
+    pairs = list(S.nacs) + [(n, m) for (m, n) in S.nacs]
+    g, d, info = ctx.gradients_and_couplings(list(range(S.nstates)), pairs, S.dh, S.dL)
+    for k in range(S.nstates):
+        assert np.abs(g[k] - grads[k]).max() < 1e-9
+    for i, p in enumerate(pairs):
+        assert np.abs(d[i] - nacs[p]).max() < 1e-9
