@@ -2,9 +2,10 @@
 //
 // * gemm_f64: FP64 matrix-core (v_mfma_f64_16x16x4_f64) GEMM over strided
 //   operands.  A 64x64 output tile per 256-thread workgroup (4 wave64s, each
-//   32x32 = 2x2 MFMA tiles), K staged through LDS in slabs of 16.  Global
-//   loads are mapped so that consecutive lanes walk the operand's unit-stride
-//   dimension.
+//   32x32 = 2x2 MFMA tiles), K staged through LDS in slabs of 32 (16 for
+//   short K) with the next slab's global loads in flight during the MFMAs.
+//   Global loads are mapped so that consecutive lanes walk the operand's
+//   unit-stride dimension.
 // * perm: strided N-d gather/scatter with up to four weighted inputs; used
 //   for operand packing, output permutation, linear combinations, block
 //   slices and embeddings.
@@ -12,6 +13,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <stdexcept>
+#include <type_traits>
 
 #include "exec.hpp"
 
@@ -21,9 +23,18 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, GEMM_THREADS = 256;
 
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs a) {
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+// Operand tiles are loaded from global memory into registers one K-slab
+// ahead: the loads of slab s+1 are in flight while the matrix cores work on
+// slab s from LDS.  TF32 selects FP32 products (operands rounded to FP32 on
+// the way into LDS, FP32 accumulation) instead of FP64.
+constexpr int BKMAX = 32;
+
+template <int BKT, bool F32>
+__device__ __forceinline__ void gemm_body(const GemmArgs& a,
+                                          typename std::conditional<F32, float, double>::type (*As)[BM + 1],
+                                          typename std::conditional<F32, float, double>::type (*Bs)[BN + 1]) {
+  typedef typename std::conditional<F32, float, double>::type T;
+  typedef T v4 __attribute__((ext_vector_type(4)));
   const int64_t split = a.splits > 1 ? blockIdx.z : 0;
   const int64_t bz = a.splits > 1 ? 0 : blockIdx.z;
   const int64_t m0 = (int64_t)blockIdx.y * BM;
@@ -39,43 +50,69 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs a) {
   const int wn = (wave & 1) * 32;
   const bool a_kfast = (a.sAk == 1);
   const bool b_nfast = (a.sBn == 1) || (a.sBk != 1);
-  d4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+  constexpr int EA = BM * BKT / GEMM_THREADS, EB = BN * BKT / GEMM_THREADS;
+  double ra[EA], rb[EB];
+  // element e of this thread: (row, k) of the A slab and (k, col) of the B
+  // slab, consecutive threads along each operand's unit-stride index
+  auto a_pos = [&](int e, int& mm, int& kk) {
+    const int idx = tid + e * GEMM_THREADS;
+    if (a_kfast) {
+      kk = idx % BKT;
+      mm = idx / BKT;
+    } else {
+      mm = idx % BM;
+      kk = idx / BM;
+    }
+  };
+  auto b_pos = [&](int e, int& nn, int& kk) {
+    const int idx = tid + e * GEMM_THREADS;
+    if (b_nfast) {
+      nn = idx % BN;
+      kk = idx / BN;
+    } else {
+      kk = idx % BKT;
+      nn = idx / BKT;
+    }
+  };
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < (BM * BK) / GEMM_THREADS; ++e) {
-      const int idx = tid + e * GEMM_THREADS;
+    for (int e = 0; e < EA; ++e) {
       int mm, kk;
-      if (a_kfast) {
-        kk = idx % BK;
-        mm = idx / BK;
-      } else {
-        mm = idx % BM;
-        kk = idx / BM;
-      }
+      a_pos(e, mm, kk);
       const int64_t gm = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gm < a.M && gk < kend) ? A[gm * a.sAm + gk * a.sAk] : 0.0;
+      ra[e] = (gm < a.M && gk < kend) ? A[gm * a.sAm + gk * a.sAk] : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < (BN * BK) / GEMM_THREADS; ++e) {
-      const int idx = tid + e * GEMM_THREADS;
+    for (int e = 0; e < EB; ++e) {
       int nn, kk;
-      if (b_nfast) {
-        nn = idx % BN;
-        kk = idx / BN;
-      } else {
-        kk = idx % BK;
-        nn = idx / BK;
-      }
+      b_pos(e, nn, kk);
       const int64_t gn = n0 + nn, gk = k0 + kk;
-      Bs[kk][nn] = (gn < a.N && gk < kend) ? B[gk * a.sBk + gn * a.sBn] : 0.0;
+      rb[e] = (gn < a.N && gk < kend) ? B[gk * a.sBk + gn * a.sBn] : 0.0;
+    }
+  };
+  v4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
+  if (kbeg < kend) load(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BKT) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      int mm, kk;
+      a_pos(e, mm, kk);
+      As[kk][mm] = (T)ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      int nn, kk;
+      b_pos(e, nn, kk);
+      Bs[kk][nn] = (T)rb[e];
     }
     __syncthreads();
+    if (k0 + BKT < kend) load(k0 + BKT);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
+    for (int kk = 0; kk < BKT; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double af[2], bf[2];
+      T af[2], bf[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         af[t] = As[kr][wm + t * 16 + (lane & 15)];
@@ -84,119 +121,15 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  if (a.splits > 1) {
-    double* P = a.P + split * a.M * a.N;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = m0 + wm + i * 16 + r * 4 + (lane >> 4);
-          const int64_t col = n0 + wn + j * 16 + (lane & 15);
-          if (row < a.M && col < a.N) P[row * a.N + col] = a.alpha * acc[i][j][r];
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (F32)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
-    return;
-  }
-  const double* Cin = a.Cin ? a.Cin + bz * a.sCb : nullptr;
-  double* C = a.C + bz * a.sCb;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // v_mfma_f64_16x16x4_f64: lane l, register r holds D[4 r + l / 16][l % 16]
-        const int64_t row = m0 + wm + i * 16 + r * 4 + (lane >> 4);
-        const int64_t col = n0 + wn + j * 16 + (lane & 15);
-        if (row < a.M && col < a.N) {
-          double v = a.alpha * acc[i][j][r];
-          if (Cin) v += a.beta * Cin[row * a.sCm + col * a.sCn];
-          C[row * a.sCm + col * a.sCn] = v;
-        }
-      }
-}
-
-// Reduced-precision variant: FP64 operands are rounded to FP32 as they are
-// staged into LDS, multiplied on the FP32 matrix cores
-// (v_mfma_f32_16x16x4_f32) with FP32 accumulation, and the result is written
-// back in FP64.  Same tiling and operand mapping as gemm_f64_kernel.
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_kernel(GemmArgs a) {
-  __shared__ float As[BK][BM + 1];
-  __shared__ float Bs[BK][BN + 1];
-  const int64_t split = a.splits > 1 ? blockIdx.z : 0;
-  const int64_t bz = a.splits > 1 ? 0 : blockIdx.z;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
-  const double* A = a.A + bz * a.sAb;
-  const double* B = a.B + bz * a.sBb;
-  const int64_t kbeg = a.splits > 1 ? split * a.kchunk : 0;
-  const int64_t kend = a.splits > 1 ? min(a.K, kbeg + a.kchunk) : a.K;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = (wave >> 1) * 32;
-  const int wn = (wave & 1) * 32;
-  const bool a_kfast = (a.sAk == 1);
-  const bool b_nfast = (a.sBn == 1) || (a.sBk != 1);
-  f4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll
-    for (int e = 0; e < (BM * BK) / GEMM_THREADS; ++e) {
-      const int idx = tid + e * GEMM_THREADS;
-      int mm, kk;
-      if (a_kfast) {
-        kk = idx % BK;
-        mm = idx / BK;
-      } else {
-        mm = idx % BM;
-        kk = idx / BM;
-      }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gm < a.M && gk < kend) ? (float)A[gm * a.sAm + gk * a.sAk] : 0.0f;
-    }
-#pragma unroll
-    for (int e = 0; e < (BN * BK) / GEMM_THREADS; ++e) {
-      const int idx = tid + e * GEMM_THREADS;
-      int nn, kk;
-      if (b_nfast) {
-        nn = idx % BN;
-        kk = idx / BN;
-      } else {
-        kk = idx % BK;
-        nn = idx / BK;
-      }
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      Bs[kk][nn] = (gn < a.N && gk < kend) ? (float)B[gk * a.sBk + gn * a.sBn] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      float af[2], bf[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        af[t] = As[kr][wm + t * 16 + (lane & 15)];
-        bf[t] = Bs[kr][wn + t * 16 + (lane & 15)];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
-  // v_mfma_f32_16x16x4_f32: lane l, register r holds D[4 (l / 16) + r][l % 16]
   double* out = a.splits > 1 ? a.P + split * a.M * a.N : a.C + bz * a.sCb;
   const double* Cin = (a.splits > 1 || !a.Cin) ? nullptr : a.Cin + bz * a.sCb;
   const int64_t sm = a.splits > 1 ? a.N : a.sCm, sn = a.splits > 1 ? 1 : a.sCn;
@@ -206,7 +139,10 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_kernel(GemmArgs a) {
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        // output layout: v_mfma_f64_16x16x4_f64 puts D[4 r + l / 16][l % 16]
+        // in lane l, register r; v_mfma_f32_16x16x4_f32 puts D[4 (l / 16) + r][l % 16]
+        const int rr = F32 ? (lane >> 4) * 4 + r : r * 4 + (lane >> 4);
+        const int64_t row = m0 + wm + i * 16 + rr;
         const int64_t col = n0 + wn + j * 16 + (lane & 15);
         if (row < a.M && col < a.N) {
           double v = a.alpha * (double)acc[i][j][r];
@@ -214,6 +150,30 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_kernel(GemmArgs a) {
           out[row * sm + col * sn] = v;
         }
       }
+}
+
+// FP64 matrix-core GEMM (the contraction kernel of every device program)
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs a) {
+  __shared__ double As[BKMAX][BM + 1];
+  __shared__ double Bs[BKMAX][BN + 1];
+  if (a.K >= 256)
+    gemm_body<32, false>(a, As, Bs);
+  else
+    gemm_body<16, false>(a, As, Bs);
+}
+
+// Reduced-precision variant: FP64 operands are rounded to FP32 as they are
+// staged into LDS, multiplied on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32) with FP32 accumulation, and the result is written
+// back in FP64.  Same tiling and operand mapping as gemm_f64_kernel.
+
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_kernel(GemmArgs a) {
+  __shared__ float As[BKMAX][BM + 1];
+  __shared__ float Bs[BKMAX][BN + 1];
+  if (a.K >= 256)
+    gemm_body<32, true>(a, As, Bs);
+  else
+    gemm_body<16, true>(a, As, Bs);
 }
 
 __global__ void splitk_reduce_kernel(GemmArgs a) {
@@ -516,6 +476,61 @@ __global__ __launch_bounds__(256) void perm_fast_kernel(FastPerm f) {
   }
 }
 
+// Transposing copy: the output's unit-stride index x and the input's
+// unit-stride index y differ.  32 x 32 tiles of (y, x) go through LDS so that
+// both the reads (along y) and the writes (along x) are coalesced; the
+// remaining indices of the iteration are decoded once per tile.
+struct TransPerm {
+  PermArgs a;
+  int dx, dy;                    // iteration dims of the output / input unit strides
+  uint32_t ntx, nty, nrest;      // tiles along x, y; product of the other dims
+  int nr;                        // number of other dims
+  int rd[MAXD];                  // their iteration dims (innermost last)
+  uint32_t rdim[MAXD], rmag[MAXD], rsh[MAXD];
+};
+
+__global__ __launch_bounds__(256) void perm_transpose_kernel(TransPerm t) {
+  __shared__ double tile[32][33];
+  const PermArgs& a = t.a;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const uint32_t ntiles = t.ntx * t.nty;
+  const uint32_t nblk = ntiles * t.nrest;
+  for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    uint32_t rest = blk / ntiles;
+    const uint32_t tt = blk - rest * ntiles;
+    const uint32_t by = tt / t.ntx, bx = tt - by * t.ntx;
+    int64_t ibase = 0, obase = 0;
+    for (int q = t.nr - 1; q >= 0; --q) {
+      const uint32_t qd = fast_div(rest, t.rmag[q], t.rsh[q]);
+      const int64_t x = (int64_t)(rest - qd * t.rdim[q]);
+      rest = qd;
+      ibase += x * a.istr[0][t.rd[q]];
+      obase += x * a.ostr[t.rd[q]];
+    }
+    const int64_t X = a.dim[t.dx], Y = a.dim[t.dy];
+    const int64_t x0 = (int64_t)bx * 32, y0 = (int64_t)by * 32;
+    // read: consecutive lanes along y (unit stride in the input)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t y = y0 + tx, x = x0 + ty + 8 * i;
+      if (y < Y && x < X) tile[ty + 8 * i][tx] = a.in[0][ibase + y * a.istr[0][t.dy] + x * a.istr[0][t.dx]];
+    }
+    __syncthreads();
+    // write: consecutive lanes along x (unit stride in the output)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t x = x0 + tx, y = y0 + ty + 8 * i;
+      if (y < Y && x < X) {
+        const int64_t o = obase + x * a.ostr[t.dx] + y * a.ostr[t.dy];
+        double v = a.coef[0] * tile[tx][ty + 8 * i];
+        if (a.addend) v += a.beta * a.addend[o];
+        a.out[o] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 void launch_perm(const PermArgs& in, hipStream_t s) {
   if (in.total <= 0) return;
   // merge neighbouring dimensions that are contiguous in the output and in
@@ -536,6 +551,45 @@ void launch_perm(const PermArgs& in, hipStream_t s) {
     --a.nd;
   }
   const int64_t lim = (int64_t)1 << 31;
+  auto magic = [](uint64_t dd, uint32_t& mag, uint32_t& sh) {
+    sh = 0;
+    while ((1ull << sh) < dd) ++sh;
+    mag = (uint32_t)(((1ull << 32) * ((1ull << sh) - dd)) / dd + 1);
+  };
+  // single input whose unit-stride index is not the output's: tiled transpose
+  if (a.total < lim && a.nin == 1 && a.nd >= 2) {
+    int dx = -1, dy = -1;
+    for (int d = 0; d < a.nd; ++d) {
+      if (a.ostr[d] == 1 && a.dim[d] > 1) dx = d;
+      if (a.istr[0][d] == 1 && a.dim[d] > 1) dy = d;
+    }
+    if (dx >= 0 && dy >= 0 && dx != dy && a.dim[dx] >= 8 && a.dim[dy] >= 8) {
+      TransPerm t{};
+      t.a = a;
+      t.dx = dx;
+      t.dy = dy;
+      t.ntx = (uint32_t)((a.dim[dx] + 31) / 32);
+      t.nty = (uint32_t)((a.dim[dy] + 31) / 32);
+      t.nr = 0;
+      uint64_t rest = 1;
+      for (int d = 0; d < a.nd; ++d) {
+        if (d == dx || d == dy) continue;
+        t.rd[t.nr] = d;
+        t.rdim[t.nr] = (uint32_t)a.dim[d];
+        magic((uint64_t)a.dim[d], t.rmag[t.nr], t.rsh[t.nr]);
+        rest *= (uint64_t)a.dim[d];
+        ++t.nr;
+      }
+      t.nrest = (uint32_t)rest;
+      const uint64_t nblk = (uint64_t)t.ntx * t.nty * rest;
+      if (nblk < ((uint64_t)1 << 31)) {
+        const unsigned grid = (unsigned)std::min<uint64_t>(nblk, 65536);
+        hipLaunchKernelGGL(perm_transpose_kernel, dim3(grid), dim3(256), 0, s, t);
+        check(hipGetLastError(), "transpose launch");
+        return;
+      }
+    }
+  }
   if (a.total < lim && a.nin >= 1 && a.nin <= 4) {
     FastPerm f{};
     f.a = a;

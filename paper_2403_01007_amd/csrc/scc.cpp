@@ -714,11 +714,14 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
           c->cp(keepR[k], c->R[k], nst);
           c->cp(keepL[k], c->Lv[k], nst);
         }
+        // the displaced solves need O to ~1e-8 only (h = 1e-4; Broyden
+        // updates refine the Jacobian afterwards)
+        const double tol_fd = std::max(tol_it, 1e-8);
         for (int p = 0; p < np; ++p) {
           std::vector<double> zp = z;
           zp[p] += h;
           set_scc_inputs(c, zp, false);
-          rc = excited_at_fixed_zeta(c, tol_it, maxit, true, iters, false);
+          rc = excited_at_fixed_zeta(c, tol_fd, maxit, true, iters, false);
           if (rc) return rc;
           std::vector<double> Op = pair_overlaps(c);
           for (int q = 0; q < np; ++q) Jz[q * np + p] = (Op[q] - O[q]) / h;
