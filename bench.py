@@ -38,6 +38,7 @@ def learned_main(args):
     ns, npair = S.nstates, S.nstates * (S.nstates - 1) // 2
 
     def solve(x, guess=None):
+        nonlocal ctx
         h, L = S.at(x)
         ctx.set_hamiltonian_fixed_basis(torch.as_tensor(h, device=dev), torch.as_tensor(L, device=dev))
         torch.cuda.synchronize()
@@ -97,6 +98,11 @@ def learned_main(args):
     plain, learned = [], []
     for x in Xte:
         plain.append(solve(x))
+    # a fresh context for the learned starts: each held-out geometry inherits
+    # only what the previous learned solve left (as along a trajectory)
+    ctx.close()
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11)
+    for x in Xte:
         c0 = time.perf_counter()
         yp = net.forward(x[None, :]).to(torch.float64)
         tg = pca_expand(mt, Ut, yp[:, :kt])[0]

@@ -154,8 +154,10 @@ int scc_ground(scc_ctx* ctx, const double* guess_t, double* e0, scc_info* info);
  * guess: NULL (plain start: CCSD states at zeta = 0 from unit vectors on
  * the lowest singles) or [nstates][1 + nov + nov^2] right vectors followed
  * by [npairs] zeta values; the solve then starts there (amplitudes from the
- * preceding scc_ground or scc_excited) and falls back to the plain start,
- * with info->fallback_used = 1, if it does not converge. */
+ * preceding scc_ground or scc_excited; the SCC Jacobian dO/dzeta of the
+ * context's previous solve, if any, seeds the zeta updates) and falls back
+ * to the plain start, with info->fallback_used = 1, if it does not
+ * converge. */
 int scc_excited(scc_ctx* ctx, int nstates, const double* guess, double* energies, double* zeta, scc_info* info);
 
 /* Lagrange multipliers of the gradient of state n (kind = 0, m ignored) or

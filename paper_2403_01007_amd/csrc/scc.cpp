@@ -288,7 +288,10 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
   c->put(m.t2, x + nov);
   c->run(m.p_res);
   c->pool_used = mark;
-  if (it >= maxit) return SCC_ENOCONV;
+  if (it >= maxit) {
+    c->err = "ground-state iterations did not converge";
+    return SCC_ENOCONV;
+  }
   return SCC_OK;
 }
 
@@ -538,6 +541,7 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     }
   }
   c->pool_used = mark;
+  c->err = "Davidson iterations did not converge";
   return SCC_ENOCONV;
 }
 
@@ -679,10 +683,11 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
     bool conv = false;
     double omax_prev = 1.0;
     for (int it = 0; it < c->opt.max_iter && !conv; ++it) {
-      // inexact inner solves while the constraint is far from satisfied
-      // (the first pass, at zeta = 0 from converged CCSD states, is tight: it
-      // is the base point of the finite-difference Jacobian)
-      const double tol_it = it == 0 ? tol : std::max(tol, std::min(1e-5, 1e-3 * omax_prev));
+      // inexact inner solves while the constraint is far from satisfied;
+      // the pass that is the base point of a finite-difference Jacobian is
+      // tight (a Jacobian carried over from a previous solve needs none)
+      const bool fd_base = it == 0 && Jz.empty();
+      const double tol_it = fd_base ? tol : std::max(tol, std::min(1e-5, 1e-3 * omax_prev));
       for (int k = 0; k < ns; ++k) c->cp(prev[k], c->R[k], nst);
       set_scc_inputs(c, z, true);
       rc = excited_at_fixed_zeta(c, tol_it, maxit, true, iters, false);
@@ -755,7 +760,10 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
     }
     c->pool_used = mark;
     c->zeta = z;
-    if (!conv) return SCC_ENOCONV;
+    if (!conv) {
+      c->err = "SCC iterations did not converge";
+      return SCC_ENOCONV;
+    }
     // left eigenvectors once, at the converged (zeta, X3) point, started
     // from the right vectors
     set_scc_inputs(c, z, false);
@@ -774,9 +782,15 @@ int excited_solve(scc_ctx* c, scc_info* info) {
   int iters = 0, rc;
   if (c->opt.precision == 1) {
     c->ex->set_lowp(true);
-    rc = excited_pass(c, std::max(tol, LOWP_TOL), std::max(tov, LOWP_TOL), false, iters);
+    try {
+      rc = excited_pass(c, std::max(tol, LOWP_TOL), std::max(tov, LOWP_TOL), false, iters);
+    } catch (const SccError& e) {
+      rc = e.code;
+    }
     c->ex->set_lowp(false);
-    if (rc) return rc;
+    // a reduced-precision pass that stalls at its own rounding level still
+    // leaves a good starting point for the FP64 refinement
+    if (rc && rc != SCC_ENOCONV) return rc;
     rc = excited_pass(c, tol, tov, true, iters);
   } else {
     rc = excited_pass(c, tol, tov, false, iters);
@@ -927,7 +941,9 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
       if (tr < 10 * tol || ++checks > 3) {
         relres = tr;
         c->pool_used = mark;
-        return tr < 10 * tol ? SCC_OK : SCC_ENOCONV;
+        if (tr < 10 * tol) return SCC_OK;
+        c->err = "Krylov solve: true residual stays above the tolerance";
+        return SCC_ENOCONV;
       }
       // continue from the true residual (its direction re-seeds the space)
       Minv(r, z);
@@ -965,15 +981,19 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
       Minv(rc.C + (int64_t)(rc.k - 1) * n, z);
     A(z, w);
     const double w0 = std::sqrt(c->dot(w, w, n));
-    // orthogonalise w against the stored c_i (twice), mirror on z
+    // orthogonalise w against the stored c_i, mirror on z; a second pass
+    // only when the first removed most of w ("twice is enough")
+    double wn = w0;
     for (int pass = 0; pass < 2; ++pass) {
+      const double before = wn;
       auto be = multi_dot(c, rc.C, rc.k, n, w);
       std::vector<double> nb(be.size());
       for (size_t i = 0; i < be.size(); ++i) nb[i] = -be[i];
       multi_axpy(c, rc.C, rc.k, n, nb, rc.coef, w);
       multi_axpy(c, rc.U, rc.k, n, nb, rc.coef, z);
+      wn = std::sqrt(c->dot(w, w, n));
+      if (wn > 0.5 * before) break;
     }
-    double wn = std::sqrt(c->dot(w, w, n));
     if (!(wn > 1e-12 * w0)) {
       // the Krylov space is (numerically) invariant: confirm with the true residual
       relres = 0.0;
@@ -991,7 +1011,9 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
     c->axpby(-al, cn, 1.0, r, n);
   }
   c->pool_used = mark;
-  return relres < tol ? SCC_OK : SCC_ENOCONV;
+  if (relres < tol) return SCC_OK;
+  c->err = "Krylov solve: iteration limit or space capacity reached";
+  return SCC_ENOCONV;
 }
 
 // ---------------------------------------------------------------------------
@@ -1183,11 +1205,13 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   const int maxg = std::max(c->opt.max_iter, c->rec_lag.cap);
   int rc;
   if (c->opt.precision == 1) {
-    // FP32-product pass, then FP64 refinement from its solution
+    // FP32-product pass, then FP64 refinement from its solution (the FP32
+    // pass may stall above its target, at the level of its own rounding:
+    // the refinement starts from wherever it got)
     c->ex->set_lowp(true);
     rc = gcr(c, c->rec_lag, apply, prec, b, x, std::max(c->opt.tol_residual, LOWP_TOL), maxg, iters, rel);
     c->ex->set_lowp(false);
-    if (rc == SCC_OK) {
+    if (rc == SCC_OK || rc == SCC_ENOCONV) {
       int it2 = 0;
       rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, it2, rel, true);
       iters += it2;
@@ -1371,13 +1395,16 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
         if (!zin[j]) continue;
         first[j] = 0;
         const double w0 = std::sqrt(c->dot(W[j], W[j], n));
+        double wn = w0;
         for (int pass = 0; pass < 2; ++pass) {
+          const double before = wn;
           auto be = multi_dot(c, C[j], k[j], n, W[j]);
           for (auto& v : be) v = -v;
           multi_axpy(c, C[j], k[j], n, be, cf[j], W[j]);
           multi_axpy(c, U[j], k[j], n, be, cf[j], Z[j]);
+          wn = std::sqrt(c->dot(W[j], W[j], n));
+          if (wn > 0.5 * before) break;
         }
-        const double wn = std::sqrt(c->dot(W[j], W[j], n));
         if (!(wn > 1e-12 * w0)) {
           force[j] = 1;  // invariant space: confirm on the true residual
           continue;
@@ -1829,7 +1856,9 @@ int scc_excited(scc_ctx* c, int nstates, const double* guess, double* energies, 
       for (double x : z) finite = finite && std::isfinite(x);
       if (finite) {
         c->zeta = z;
-        c->Jz.clear();
+        // the zeta Jacobian of the previous solve (a nearby geometry along a
+        // trajectory) seeds the Newton/Broyden iteration
+        if (c->Jz.size() != (size_t)np * np) c->Jz.clear();
         try {
           int iters = 0;
           rc = excited_pass(c, c->opt.tol_residual, c->opt.tol_overlap, true, iters);

@@ -113,15 +113,20 @@ def test_learned_guess_reduces_iterations_and_keeps_results():
     net = Mlp(S.ncoord, nh, nout, p0)
     losses = net.train(Xtr, Y, np.stack([rng.permutation(ntr)[:16] for _ in range(1500)]), lr=1e-3)
     assert losses[-50:].mean() < 0.1 * losses[:10].mean()
-    gains = []
-    for x in family_geometries(S.ncoord, range(20000, 20004)):
+    held = family_geometries(S.ncoord, range(20000, 20004))
+    plain = []
+    for x in held:
         ctx.set_hamiltonian_fixed_basis(*S.at(x))
         E0, _, i0 = ctx.excited()
-        it_plain = i0.iterations
-        ctx.set_hamiltonian_fixed_basis(*S.at(x))
+        plain.append((E0, i0.iterations))
+    # learned starts in a context of their own, geometry after geometry
+    ctx2 = Context(S.o, S.v, S.nj, ns, tol=1e-10, tol_overlap=1e-11)
+    gains = []
+    for x, (E0, it_plain) in zip(held, plain):
+        ctx2.set_hamiltonian_fixed_basis(*S.at(x))
         y = net.forward(x[None, :]).to(torch.float64)
-        _, ig = ctx.ground(pca_expand(mt, Ut, y[:, :k])[0])
-        E1, _, i1 = ctx.excited(torch.cat([pca_expand(mr, Ur, y[:, k:2 * k])[0], y[0, 2 * k:]]))
+        _, ig = ctx2.ground(pca_expand(mt, Ut, y[:, :k])[0])
+        E1, _, i1 = ctx2.excited(torch.cat([pca_expand(mr, Ur, y[:, k:2 * k])[0], y[0, 2 * k:]]))
         assert np.abs(E1 - E0).max() < 1e-9
         assert ig.fallback_used == 0 and i1.fallback_used == 0
         gains.append((it_plain, i1.iterations + ig.iterations))
