@@ -69,14 +69,15 @@ typedef struct scc_options {
   int max_iter;          /* iteration limit of each solver */
   int scc;               /* 1: SCCSD(E); 0: plain CCSD / EOM-CCSD */
   int verbose;           /* 1: per-iteration log on stderr */
-  int precision;         /* 0: FP64 throughout.  1: the dense contractions
+  int precision;         /* 0: FP64 throughout.  1: in the ground and
+                            excited-state solves the dense contractions
                             (every GEMM with M, N, K >= 64: ladder, ring,
                             hole-hole, Fock-dressed) take FP32 products with
-                            FP32 accumulation on the matrix cores until each
-                            solver reaches max(tol_residual, 1e-6); the
-                            solve is then refined in FP64 from that point.
-                            Residual norms, DIIS, subspace eigenproblems and
-                            orthogonalisation stay in FP64 in both modes. */
+                            FP32 accumulation on the matrix cores until the
+                            solve reaches max(tol_residual, 1e-6); it is then
+                            refined in FP64 from that point.  Residual norms,
+                            DIIS, subspace eigenproblems, orthogonalisation
+                            and the multiplier equations stay in FP64. */
   int eager;             /* 0: every device program (the residual, the
                             transformations, the Lagrangian products...) is
                             captured once as a HIP graph and replayed.
@@ -191,7 +192,7 @@ int scc_nac(scc_ctx* ctx, int m, int n, int ncoord, const double* dh, const doub
  * serves all of them; each target keeps its own Krylov recurrence.
  * states: host int[ngrad]; pairs: host int[2 * npair] as (m, n);
  * grads: device double[ngrad][ncoord]; nacs: device double[npair][ncoord].
- * With precision = 1 the targets are solved one at a time. */
+ * The multiplier equations are solved in FP64 in every precision mode. */
 int scc_gradients_and_couplings(scc_ctx* ctx, int ngrad, const int* states, int npair, const int* pairs, int ncoord,
                                 const double* dh, const double* dchol, double* grads, double* nacs, scc_info* info);
 

@@ -182,6 +182,7 @@ struct scc_ctx {
   }
   double tensor_scalar(int id) { return zero(id) ? 0.0 : host_scalar(tp(id)); }
   void set_scalar(int id, double v) { launch_fill(tp(id), 1, v, s); }
+  void set_scalar_ptr(double* p, double v) { launch_fill(p, 1, v, s); }
   double dot(const double* x, const double* y, int64_t n) {
     launch_dot(x, y, n, 1.0, nullptr, 0.0, dsc, partials, s);
     return host_scalar(dsc);
@@ -1089,26 +1090,69 @@ void lag_rhs(scc_ctx* c, const std::vector<int64_t>& offs, int kind, int mm, int
   }
 }
 
-// block-diagonal preconditioner: orbital-energy differences (shifted by
-// omega_k on the state blocks) on the amplitude blocks, identity elsewhere
-void lag_prec(scc_ctx* c, const std::vector<Seg>& segs, const std::vector<int64_t>& offs, const double* in,
-              double* out) {
+// Preconditioner of the multiplier equations J^T lambda = b (parameter-space
+// residual in, multiplier space out).  Amplitude block: orbital-energy
+// differences.  Each excited state k carries the bordered block
+//     [ (Hbar - E_k)^T   -Lam_k ] [lambda_k]   [f]   (rows of R_k)
+//     [ -R_k^T             0    ] [  mu_k  ] = [g]   (row of E_k)
+// whose leading part is replaced by Dk = diag(D - omega_k) (floored) and
+// solved exactly through its Schur complement:
+//     mu = -(g + R.Dk^-1 f) / (R.Dk^-1 Lam),  lambda = Dk^-1 (f + Lam mu).
+// zeta / O_kl rows: identity.
+struct LagPrec {
+  std::vector<double*> q;   // Dk^-1 Lam_k per state [1 + nov + nov^2]
+  std::vector<double> den;  // R_k . Dk^-1 Lam_k
+};
+
+void lag_state_dinv(scc_ctx* c, int k, const double* in, double* out) {
   const int64_t nov = c->sz.nov;
   double* dzero = c->dsc + 8;
-  c->fill(dzero, 1, 0.0);
+  const double shift = c->E[k] - c->E0;
+  launch_precond(in, dzero, shift, 0.05, out, 1, c->s);
+  launch_precond(in + 1, c->D, shift, 0.05, out + 1, nov, c->s);
+  launch_precond(in + 1 + nov, c->D + nov, shift, 0.05, out + 1 + nov, nov * nov, c->s);
+}
+
+LagPrec lag_prec_setup(scc_ctx* c) {
+  LagPrec P;
+  const int ns = c->m.d.ns;
+  c->fill(c->dsc + 8, 1, 0.0);
+  for (int k = 0; k < ns; ++k) {
+    double* q = c->alloc(c->sz.nst);
+    lag_state_dinv(c, k, c->Lv[k], q);
+    P.q.push_back(q);
+    P.den.push_back(c->dot(c->R[k], q, c->sz.nst));
+  }
+  return P;
+}
+
+void lag_prec(scc_ctx* c, const LagPrec& P, const std::vector<Seg>& segs, const std::vector<int64_t>& offs,
+              const double* in, double* out) {
+  const int64_t nov = c->sz.nov, nst = c->sz.nst;
+  const int ns = c->m.d.ns;
+  c->fill(c->dsc + 8, 1, 0.0);
+  // amplitude block and zeta rows
   for (size_t i = 0; i < segs.size(); ++i) {
     const Seg& sg = segs[i];
+    if (sg.kind > 0) continue;
     if (!sg.active) {
       c->fill(out + offs[i], sg.n, 0.0);
-      continue;
-    }
-    if (sg.kind < 0) {
+    } else if (sg.kind < 0) {
       c->cp(out + offs[i], in + offs[i], sg.n);
-      continue;
+    } else {
+      const double* Dseg = sg.comp == 1 ? c->D : c->D + nov;
+      launch_precond(in + offs[i], Dseg, 0.0, 0.05, out + offs[i], sg.n, c->s);
     }
-    double shift = sg.kind == 0 ? 0.0 : (c->E[sg.kind - 1] - c->E0);
-    const double* Dseg = sg.comp == 0 ? dzero : (sg.comp == 1 ? c->D : c->D + nov);
-    launch_precond(in + offs[i], Dseg, shift, 0.05, out + offs[i], sg.n, c->s);
+  }
+  // state blocks with their normalisation border
+  for (int k = 0; k < ns; ++k) {
+    const int64_t sb = offs[2 + 4 * k], eb = offs[2 + 4 * k + 3];
+    lag_state_dinv(c, k, in + sb, out + sb);
+    const double rf = c->dot(c->R[k], out + sb, nst);
+    const double g = c->host_scalar(in + eb);
+    const double mu = std::fabs(P.den[k]) > 1e-300 ? -(g + rf) / P.den[k] : 0.0;
+    c->axpby(mu, P.q[k], 1.0, out + sb, nst);
+    c->set_scalar_ptr(out + eb, mu);
   }
 }
 
@@ -1182,7 +1226,8 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
     off += sg.n;
   }
   lag_rhs(c, offs, kind, mm, nn, b);
-  auto prec = [&](const double* in, double* out) { lag_prec(c, segs, offs, in, out); };
+  LagPrec lp = lag_prec_setup(c);
+  auto prec = [&](const double* in, double* out) { lag_prec(c, lp, segs, offs, in, out); };
   auto apply = [&](const double* in, double* out) {
     for (size_t i = 0; i < segs.size(); ++i) {
       if (segs[i].active)
@@ -1204,21 +1249,11 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   double rel = 0;
   const int maxg = std::max(c->opt.max_iter, c->rec_lag.cap);
   int rc;
-  if (c->opt.precision == 1) {
-    // FP32-product pass, then FP64 refinement from its solution (the FP32
-    // pass may stall above its target, at the level of its own rounding:
-    // the refinement starts from wherever it got)
-    c->ex->set_lowp(true);
-    rc = gcr(c, c->rec_lag, apply, prec, b, x, std::max(c->opt.tol_residual, LOWP_TOL), maxg, iters, rel);
-    c->ex->set_lowp(false);
-    if (rc == SCC_OK || rc == SCC_ENOCONV) {
-      int it2 = 0;
-      rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, it2, rel, true);
-      iters += it2;
-    }
-  } else {
-    rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, iters, rel);
-  }
+  // The multiplier equations are solved in FP64 in every precision mode:
+  // with FP32 products the Krylov recurrence of this bordered system drifts
+  // away from its true residual (directions of large norm amplify the
+  // product rounding), so a reduced-precision pass is no usable start.
+  rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, iters, rel);
   if (rc) {
     c->pool_used = mark;
     return rc;
@@ -1289,7 +1324,8 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
       off += sg.n;
     }
   }
-  auto prec = [&](const double* in, double* out) { lag_prec(c, segs, offs, in, out); };
+  LagPrec lp = lag_prec_setup(c);
+  auto prec = [&](const double* in, double* out) { lag_prec(c, lp, segs, offs, in, out); };
   // out_j = J^T in_j for the listed slots (at most nbt), other slots zero
   auto applyB = [&](const std::vector<const double*>& in, const std::vector<double*>& out) {
     for (size_t i = 0; i < segs.size(); ++i) {
@@ -1989,9 +2025,8 @@ int scc_gradients_and_couplings(scc_ctx* c, int ngrad, const int* states, int np
   }
   return guarded(c, info, [&]() -> int {
     int iters = 0;
-    int rc = c->m.nbt > 1 && c->opt.precision == 0 ? targets_solve(c, tg, ncoord, dh, dchol, iters) : SCC_EINVAL;
-    if (c->m.nbt <= 1 || c->opt.precision != 0) {
-      // one target at a time (reduced-precision mode refines each in FP64)
+    int rc = c->m.nbt > 1 ? targets_solve(c, tg, ncoord, dh, dchol, iters) : SCC_EINVAL;
+    if (c->m.nbt <= 1) {
       rc = SCC_OK;
       for (auto& t : tg) {
         scc_info inf{};
