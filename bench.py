@@ -18,15 +18,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
+PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 
 
-def stored_traffic(workload):
-    """HBM bytes per gemm_f64_kernel launch from the counter runs recorded in
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the counter runs recorded in
     profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a
     plain copy of known size); None unless they were taken over this
     workload with the kernel source as it is now."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"gemm_f64_kernel_{workload}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -189,6 +190,7 @@ def main():
     import numpy as np
     import torch
     from paper_2403_01007_amd import Context
+    from paper_2403_01007_amd.binding import GEMM_KERNEL_NAMES
     from synth_inputs import make_system
 
     S = make_system(args.workload)
@@ -255,7 +257,8 @@ def main():
         step()
         print(f"[warmup step done]", file=sys.stderr, flush=True)
     flops[0] = 0.0
-    ms0, fl0, n0 = ctx.profile(not args.no_roofline)
+    kernels = range(len(GEMM_KERNEL_NAMES))
+    before = [ctx.profile(not args.no_roofline, q) for q in kernels]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -263,22 +266,27 @@ def main():
         print(f"[timed step {k} done]", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms1, fl1, n1 = ctx.profile(False)
+    after = [ctx.profile(False, q) for q in kernels]
     s_per_geom = elapsed / args.steps
-    gemm_s = (ms1 - ms0) / 1e3
-    gemm_fl = fl1 - fl0
+    # per GEMM kernel over the timed steps: seconds, flops, launches; the
+    # roofline is that of the kernel with the most time
+    per_kernel = {GEMM_KERNEL_NAMES[q]: ((after[q][0] - before[q][0]) / 1e3, after[q][1] - before[q][1],
+                                         after[q][2] - before[q][2]) for q in kernels}
+    top = max(per_kernel, key=lambda k: per_kernel[k][0])
+    gemm_s, gemm_fl, gemm_n = per_kernel[top]
     achieved = gemm_fl / gemm_s / 1e12 if gemm_s > 0 else 0.0
+    peak = PEAK_FP64_MFMA if "f64" in top else PEAK_FP32_MFMA
 
     # flops of one residual evaluation (for the CPU-baseline scaling)
     nov = S.o * S.v
     t_zero = np.zeros(nov + nov * nov)
-    ctx.profile(True)
-    a_ms, a_fl, _ = ctx.profile(True)
+    a_fl = sum(ctx.profile(True, q)[1] for q in kernels)
     ctx.eval_residual(t_zero)
-    b_ms, b_fl, _ = ctx.profile(False)
+    b_fl = sum(ctx.profile(True, q)[1] for q in kernels)
+    ctx.profile(False)
     res_flops = b_fl - a_fl
 
-    traffic = stored_traffic(args.workload)
+    traffic = stored_traffic(top, args.workload)
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import cc
@@ -311,9 +319,12 @@ def main():
                    "ncoord": S.ncoord, "nacs": len(S.nacs), "precision": args.precision, "guess": "mp2/unit",
                    "generator": S.reading},
         "tflops_contractions": (flops[0] / args.steps) / s_per_geom / 1e12,
-        "roofline": {"bound": "mfma", "kernel": "gemm_f64_kernel", "achieved": achieved,
-                     "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA,
-                     "traffic": traffic, "launches": n1 - n0, "kernel_seconds": gemm_s},
+        "roofline": {"bound": "mfma", "kernel": top, "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic, "launches": gemm_n, "kernel_seconds": gemm_s,
+                     "gemm_kernels": {k: {"seconds": v[0], "launches": v[2],
+                                          "tflops": v[1] / v[0] / 1e12 if v[0] > 0 else 0.0}
+                                      for k, v in per_kernel.items() if v[2] > 0}},
         "cpu_baseline": cpu,
         "energies": [float(x) for x in res["E"]],
     }

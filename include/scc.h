@@ -205,13 +205,20 @@ int scc_gradients_and_couplings(scc_ctx* ctx, int ngrad, const int* states, int 
 enum { SCC_FIELD_T = 0, SCC_FIELD_R = 1, SCC_FIELD_L = 2, SCC_FIELD_E0 = 3, SCC_FIELD_OMEGA = 4 };
 int scc_get(scc_ctx* ctx, int field, int k, double* out);
 
-/* Profiling of the FP64 MFMA contraction kernel: enable = 1 starts timing
- * every GEMM launch with HIP events on the context's stream (0 stops and
- * clears nothing).  On return (host pointers, any may be NULL): accumulated
- * kernel milliseconds, algorithmic flops (2 M N K per launch) and launches
- * since the context was created.  With the verbose option, enable = 0 also
- * prints the time per GEMM shape on stderr. */
-int scc_profile(scc_ctx* ctx, int enable, double* gemm_ms, double* gemm_flops, long long* gemm_launches);
+/* Profiling of the MFMA contraction kernels: enable = 1 starts timing every
+ * GEMM launch with HIP events on the context's stream (0 stops and clears
+ * nothing).  kernel selects the totals returned:
+ *   SCC_GEMM_F64      gemm_f64_kernel (FP64; each operand index group one
+ *                     run of dimensions)
+ *   SCC_GEMM_F64_TWO  gemm_f64_two_kernel (FP64; some group spans two runs)
+ *   SCC_GEMM_F32, SCC_GEMM_F32_TWO  the FP32-product variants (precision 1)
+ * On return (host pointers, any may be NULL): accumulated kernel
+ * milliseconds, algorithmic flops (2 M N K per launch) and launches since
+ * the context was created.  SCC_EINVAL for another kernel value.  With the
+ * verbose option, enable = 0 on a profiling context also prints the time per
+ * GEMM shape on stderr. */
+enum { SCC_GEMM_F64 = 0, SCC_GEMM_F64_TWO = 1, SCC_GEMM_F32 = 2, SCC_GEMM_F32_TWO = 3 };
+int scc_profile(scc_ctx* ctx, int enable, int kernel, double* gemm_ms, double* gemm_flops, long long* gemm_launches);
 
 /* Test hooks on the device programs (inputs/outputs device pointers):
  *   residual at given amplitudes (and zeta / X3 states when nstates > 1):

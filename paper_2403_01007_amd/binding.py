@@ -11,6 +11,9 @@ SCC_OK = 0
 ERRORS = {0: "SCC_OK", -1: "SCC_EINVAL", -2: "SCC_ESTATE", -3: "SCC_ENOCONV", -4: "SCC_ECOMPLEX",
           -5: "SCC_ESINGULAR", -6: "SCC_EDEVICE", -7: "SCC_ENOMEM"}
 FIELD_T, FIELD_R, FIELD_L, FIELD_E0, FIELD_OMEGA = 0, 1, 2, 3, 4
+# GEMM kernels whose launches scc_profile totals
+GEMM_F64, GEMM_F64_TWO, GEMM_F32, GEMM_F32_TWO = 0, 1, 2, 3
+GEMM_KERNEL_NAMES = ["gemm_f64_kernel", "gemm_f64_two_kernel", "gemm_f32acc_kernel", "gemm_f32acc_two_kernel"]
 
 EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_last_error",
                     "scc_set_hamiltonian", "scc_set_hamiltonian_fixed_basis", "scc_ground", "scc_excited", "scc_multipliers",
@@ -79,7 +82,7 @@ def load_library():
     lib.scc_eval_residual.argtypes = [P, P, P, P, P]
     lib.scc_eval_sigma.argtypes = [P, P, P]
     lib.scc_eval_left.argtypes = [P, P, P]
-    lib.scc_profile.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]
+    lib.scc_profile.argtypes = [P, I, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]
     MD = ctypes.POINTER(MlpDims)
     lib.scc_mlp_param_count.argtypes = [MD, ctypes.POINTER(ctypes.c_longlong)]
     lib.scc_mlp_workspace_bytes.argtypes = [MD, I, ctypes.POINTER(S)]
@@ -268,9 +271,9 @@ class Context:
         self._check(self.lib.scc_eval_sigma(self.h, _ptr(v), _ptr(out)), "scc_eval_sigma")
         return out
 
-    def profile(self, enable):
+    def profile(self, enable, kernel=GEMM_F64):
         ms, fl, n = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_longlong(0)
-        self._check(self.lib.scc_profile(self.h, 1 if enable else 0, ctypes.byref(ms), ctypes.byref(fl),
+        self._check(self.lib.scc_profile(self.h, 1 if enable else 0, kernel, ctypes.byref(ms), ctypes.byref(fl),
                                          ctypes.byref(n)), "scc_profile")
         return ms.value, fl.value, n.value
 

@@ -23,13 +23,34 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, GEMM_THREADS = 256;
 
+// n / d for n, d < 2^31 as (umulhi(n, m) + n) >> s with s = ceil(log2 d)
+// and m = floor(2^32 (2^s - d) / d) + 1
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t m, uint32_t s) {
+  return (__umulhi(n, m) + n) >> s;
+}
+
+// element offset of index x of a fused group (one or two runs)
+__device__ __forceinline__ int64_t imap(int64_t x, const IdxMap& m, int64_t si) {
+  if (m.D == 0) return x * si;
+  const int64_t q = (int64_t)fast_div((uint32_t)x, m.mag, m.sh);
+  return q * (int64_t)m.so + (x - q * (int64_t)m.D) * si;
+}
+
+// the same in 32 bits, for tensors of fewer than 2^31 elements and every
+// group given as two runs (a single run as D = 2^31)
+__device__ __forceinline__ uint32_t imap32(uint32_t x, const IdxMap& m, int64_t si) {
+  const uint32_t q = fast_div(x, m.mag, m.sh);
+  return q * m.so + (x - q * m.D) * (uint32_t)si;
+}
+
+constexpr int BKMAX = 32;
+
 // Operand tiles are loaded from global memory into registers one K-slab
 // ahead: the loads of slab s+1 are in flight while the matrix cores work on
 // slab s from LDS.  TF32 selects FP32 products (operands rounded to FP32 on
 // the way into LDS, FP32 accumulation) instead of FP64.
-constexpr int BKMAX = 32;
 
-template <int BKT, bool F32>
+template <int BKT, bool F32, bool TWO>
 __device__ __forceinline__ void gemm_body(const GemmArgs& a,
                                           typename std::conditional<F32, float, double>::type (*As)[BM + 1],
                                           typename std::conditional<F32, float, double>::type (*Bs)[BN + 1]) {
@@ -74,20 +95,45 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& a,
       nn = idx / BKT;
     }
   };
+  // two-run groups: 32-bit offsets; the row / column offset of each loaded
+  // element is fixed across K slabs
+  uint32_t aoff[TWO ? EA : 1], boff[TWO ? EB : 1];
+  if constexpr (TWO) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      int mm, kk;
+      a_pos(e, mm, kk);
+      const int64_t gm = m0 + mm;
+      aoff[e] = gm < a.M ? imap32((uint32_t)gm, a.mAm, a.sAm) : 0u;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      int nn, kk;
+      b_pos(e, nn, kk);
+      const int64_t gn = n0 + nn;
+      boff[e] = gn < a.N ? imap32((uint32_t)gn, a.mBn, a.sBn) : 0u;
+    }
+  }
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       int mm, kk;
       a_pos(e, mm, kk);
       const int64_t gm = m0 + mm, gk = k0 + kk;
-      ra[e] = (gm < a.M && gk < kend) ? A[gm * a.sAm + gk * a.sAk] : 0.0;
+      if constexpr (TWO)
+        ra[e] = (gm < a.M && gk < kend) ? A[aoff[e] + imap32((uint32_t)gk, a.mAk, a.sAk)] : 0.0;
+      else
+        ra[e] = (gm < a.M && gk < kend) ? A[gm * a.sAm + gk * a.sAk] : 0.0;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       int nn, kk;
       b_pos(e, nn, kk);
       const int64_t gn = n0 + nn, gk = k0 + kk;
-      rb[e] = (gn < a.N && gk < kend) ? B[gk * a.sBk + gn * a.sBn] : 0.0;
+      if constexpr (TWO)
+        rb[e] = (gn < a.N && gk < kend) ? B[boff[e] + imap32((uint32_t)gk, a.mBk, a.sBk)] : 0.0;
+      else
+        rb[e] = (gn < a.N && gk < kend) ? B[gk * a.sBk + gn * a.sBn] : 0.0;
     }
   };
   v4 acc[2][2];
@@ -130,9 +176,9 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& a,
     }
     __syncthreads();
   }
-  double* out = a.splits > 1 ? a.P + split * a.M * a.N : a.C + bz * a.sCb;
-  const double* Cin = (a.splits > 1 || !a.Cin) ? nullptr : a.Cin + bz * a.sCb;
-  const int64_t sm = a.splits > 1 ? a.N : a.sCm, sn = a.splits > 1 ? 1 : a.sCn;
+  const bool part = a.splits > 1;
+  double* out = part ? a.P + split * a.M * a.N : a.C + bz * a.sCb;
+  const double* Cin = (part || !a.Cin) ? nullptr : a.Cin + bz * a.sCb;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -146,34 +192,58 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& a,
         const int64_t col = n0 + wn + j * 16 + (lane & 15);
         if (row < a.M && col < a.N) {
           double v = a.alpha * (double)acc[i][j][r];
-          if (Cin) v += a.beta * Cin[row * a.sCm + col * a.sCn];
-          out[row * sm + col * sn] = v;
+          const int64_t o = part ? row * a.N + col
+                            : TWO ? (int64_t)(imap32((uint32_t)row, a.mCm, a.sCm) + imap32((uint32_t)col, a.mCn, a.sCn))
+                                  : row * a.sCm + col * a.sCn;
+          if (Cin) v += a.beta * Cin[o];
+          out[o] = v;
         }
       }
 }
 
-// FP64 matrix-core GEMM (the contraction kernel of every device program)
+// FP64 matrix-core GEMM (the contraction kernel of every device program):
+// every operand index group (rows, columns, summed index) is one run of
+// dimensions with one stride
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs a) {
   __shared__ double As[BKMAX][BM + 1];
   __shared__ double Bs[BKMAX][BN + 1];
   if (a.K >= 256)
-    gemm_body<32, false>(a, As, Bs);
+    gemm_body<32, false, false>(a, As, Bs);
   else
-    gemm_body<16, false>(a, As, Bs);
+    gemm_body<16, false, false>(a, As, Bs);
 }
 
-// Reduced-precision variant: FP64 operands are rounded to FP32 as they are
+// The same where some group spans two runs (read in place instead of
+// packing the operand, or writing a temporary, in the group's order)
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_two_kernel(GemmArgs a) {
+  __shared__ double As[BKMAX][BM + 1];
+  __shared__ double Bs[BKMAX][BN + 1];
+  if (a.K >= 256)
+    gemm_body<32, false, true>(a, As, Bs);
+  else
+    gemm_body<16, false, true>(a, As, Bs);
+}
+
+// Reduced-precision variants: FP64 operands are rounded to FP32 as they are
 // staged into LDS, multiplied on the FP32 matrix cores
 // (v_mfma_f32_16x16x4_f32) with FP32 accumulation, and the result is written
-// back in FP64.  Same tiling and operand mapping as gemm_f64_kernel.
-
+// back in FP64.  Same tiling and operand mapping as the FP64 kernels.
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_kernel(GemmArgs a) {
   __shared__ float As[BKMAX][BM + 1];
   __shared__ float Bs[BKMAX][BN + 1];
   if (a.K >= 256)
-    gemm_body<32, true>(a, As, Bs);
+    gemm_body<32, true, false>(a, As, Bs);
   else
-    gemm_body<16, true>(a, As, Bs);
+    gemm_body<16, true, false>(a, As, Bs);
+}
+
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_two_kernel(GemmArgs a) {
+  __shared__ float As[BKMAX][BM + 1];
+  __shared__ float Bs[BKMAX][BN + 1];
+  if (a.K >= 256)
+    gemm_body<32, true, true>(a, As, Bs);
+  else
+    gemm_body<16, true, true>(a, As, Bs);
 }
 
 __global__ void splitk_reduce_kernel(GemmArgs a) {
@@ -183,8 +253,9 @@ __global__ void splitk_reduce_kernel(GemmArgs a) {
     const int64_t row = i / a.N, col = i % a.N;
     double v = 0.0;
     for (int64_t s = 0; s < a.splits; ++s) v += a.P[s * mn + i];
-    if (a.Cin) v += a.beta * a.Cin[row * a.sCm + col * a.sCn];
-    a.C[row * a.sCm + col * a.sCn] = v;
+    const int64_t o = imap(row, a.mCm, a.sCm) + imap(col, a.mCn, a.sCn);
+    if (a.Cin) v += a.beta * a.Cin[o];
+    a.C[o] = v;
   }
 }
 
@@ -200,7 +271,10 @@ __global__ void perm_kernel(PermArgs a) {
       for (int i = 0; i < a.nin; ++i) io[i] += x * a.istr[i][d];
     }
     double v = 0.0;
-    for (int i = 0; i < a.nin; ++i) v += a.coef[i] * a.in[i][io[i]];
+    if (a.mul)
+      v = a.coef[0] * a.in[0][io[0]] * a.in[1][io[1]];
+    else
+      for (int i = 0; i < a.nin; ++i) v += a.coef[i] * a.in[i][io[i]];
     if (a.addend) v += a.beta * a.addend[oo];
     a.out[oo] = v;
   }
@@ -308,10 +382,12 @@ void launch_gemm_main(const GemmArgs& a, hipStream_t s, bool f32) {
   dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((a.M + BM - 1) / BM),
             (unsigned)(a.splits > 1 ? a.splits : a.batch));
   if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm grid too large");
-  if (f32)
-    hipLaunchKernelGGL(gemm_f32acc_kernel, grid, dim3(GEMM_THREADS), 0, s, a);
-  else
-    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(GEMM_THREADS), 0, s, a);
+  switch (gemm_kernel_id(a, f32)) {
+    case GEMM_F64: hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(GEMM_THREADS), 0, s, a); break;
+    case GEMM_F64_TWO: hipLaunchKernelGGL(gemm_f64_two_kernel, grid, dim3(GEMM_THREADS), 0, s, a); break;
+    case GEMM_F32: hipLaunchKernelGGL(gemm_f32acc_kernel, grid, dim3(GEMM_THREADS), 0, s, a); break;
+    default: hipLaunchKernelGGL(gemm_f32acc_two_kernel, grid, dim3(GEMM_THREADS), 0, s, a); break;
+  }
   check(hipGetLastError(), "gemm launch");
 }
 
@@ -406,28 +482,6 @@ void launch_gemv(const GemvArgs& g, hipStream_t s) {
   }
 }
 
-__global__ void outer_kernel(GemmArgs a, int nfast) {
-  const int64_t mn = a.M * a.N, total = mn * a.batch;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < total; lin += stride) {
-    const int64_t b = lin / mn, r = lin % mn;
-    const int64_t m = nfast ? r / a.N : r % a.M;
-    const int64_t n = nfast ? r % a.N : r / a.M;
-    double v = a.alpha * a.A[b * a.sAb + m * a.sAm] * a.B[b * a.sBb + n * a.sBn];
-    const int64_t o = b * a.sCb + m * a.sCm + n * a.sCn;
-    if (a.Cin) v += a.beta * a.Cin[o];
-    a.C[o] = v;
-  }
-}
-
-void launch_outer(const GemmArgs& a, hipStream_t s) {
-  const int64_t total = a.M * a.N * a.batch;
-  if (total <= 0) return;
-  const int nfast = (a.sCn == 1 || a.sCm != 1) ? 1 : 0;
-  hipLaunchKernelGGL(outer_kernel, dim3(grid_for(total)), dim3(256), 0, s, a, nfast);
-  check(hipGetLastError(), "outer launch");
-}
-
 void launch_combine(const double* X, int k, int64_t n, const double* coef, double* y, hipStream_t s) {
   if (k <= 0 || n <= 0) return;
   hipLaunchKernelGGL(combine_kernel, dim3(grid_for(n)), dim3(256), 0, s, X, k, n, coef, y);
@@ -442,11 +496,8 @@ struct FastPerm {
   uint32_t dim[MAXD], mag[MAXD], sh[MAXD];
 };
 
-__device__ __forceinline__ uint32_t fast_div(uint32_t n, uint32_t m, uint32_t s) {
-  return (__umulhi(n, m) + n) >> s;
-}
 
-template <int NIN>
+template <int NIN, bool MUL>
 __global__ __launch_bounds__(256) void perm_fast_kernel(FastPerm f) {
   const PermArgs& a = f.a;
   const uint32_t total = (uint32_t)a.total;
@@ -469,8 +520,12 @@ __global__ __launch_bounds__(256) void perm_fast_kernel(FastPerm f) {
       }
     }
     double v = 0.0;
+    if constexpr (MUL) {
+      v = a.coef[0] * a.in[0][io[0]] * a.in[1][io[1]];
+    } else {
 #pragma unroll
-    for (int i = 0; i < NIN; ++i) v += a.coef[i] * a.in[i][io[i]];
+      for (int i = 0; i < NIN; ++i) v += a.coef[i] * a.in[i][io[i]];
+    }
     if (a.addend) v += a.beta * a.addend[oo];
     a.out[oo] = v;
   }
@@ -557,7 +612,7 @@ void launch_perm(const PermArgs& in, hipStream_t s) {
     mag = (uint32_t)(((1ull << 32) * ((1ull << sh) - dd)) / dd + 1);
   };
   // single input whose unit-stride index is not the output's: tiled transpose
-  if (a.total < lim && a.nin == 1 && a.nd >= 2) {
+  if (a.total < lim && a.nin == 1 && !a.mul && a.nd >= 2) {
     int dx = -1, dy = -1;
     for (int d = 0; d < a.nd; ++d) {
       if (a.ostr[d] == 1 && a.dim[d] > 1) dx = d;
@@ -602,11 +657,15 @@ void launch_perm(const PermArgs& in, hipStream_t s) {
       f.mag[d] = (uint32_t)(((1ull << 32) * ((1ull << sh) - dd)) / dd + 1);
     }
     const dim3 grid(grid_for(a.total)), block(256);
-    switch (a.nin) {
-      case 1: hipLaunchKernelGGL(perm_fast_kernel<1>, grid, block, 0, s, f); break;
-      case 2: hipLaunchKernelGGL(perm_fast_kernel<2>, grid, block, 0, s, f); break;
-      case 3: hipLaunchKernelGGL(perm_fast_kernel<3>, grid, block, 0, s, f); break;
-      default: hipLaunchKernelGGL(perm_fast_kernel<4>, grid, block, 0, s, f); break;
+    if (a.mul) {
+      hipLaunchKernelGGL((perm_fast_kernel<2, true>), grid, block, 0, s, f);
+    } else {
+      switch (a.nin) {
+        case 1: hipLaunchKernelGGL((perm_fast_kernel<1, false>), grid, block, 0, s, f); break;
+        case 2: hipLaunchKernelGGL((perm_fast_kernel<2, false>), grid, block, 0, s, f); break;
+        case 3: hipLaunchKernelGGL((perm_fast_kernel<3, false>), grid, block, 0, s, f); break;
+        default: hipLaunchKernelGGL((perm_fast_kernel<4, false>), grid, block, 0, s, f); break;
+      }
     }
   } else {
     hipLaunchKernelGGL(perm_kernel, dim3(grid_for(a.total)), dim3(256), 0, s, a);
@@ -683,6 +742,47 @@ static View fuse(const std::string& l, const TensorDesc& d, const std::string& o
     if (st[p] != st[q] * d.dim[q]) return {false, size, 0};
   }
   return {true, size, st[l.find(order.back())]};
+}
+
+// Indices `order` as at most two runs of fusible dimensions: the outer run
+// (stride ostride of its last index) and the inner run (size `inner`, stride
+// `stride` of its last index); inner = 0 for a single run.
+struct View2 {
+  bool ok;
+  int64_t size, stride, inner, ostride;
+};
+
+static View2 fuse2(const std::string& l, const TensorDesc& d, const std::string& order) {
+  auto st = row_major_strides(d);
+  if (order.empty()) return {true, 1, 0, 0, 0};
+  int64_t size = 1;
+  for (char c : order) size *= d.dim[l.find(c)];
+  int breaks = 0, bpos = -1;
+  for (size_t i = 0; i + 1 < order.size(); ++i) {
+    int p = (int)l.find(order[i]), q = (int)l.find(order[i + 1]);
+    if (st[p] != st[q] * d.dim[q]) {
+      ++breaks;
+      bpos = (int)i;
+    }
+  }
+  const int64_t last = st[l.find(order.back())];
+  if (breaks == 0) return {true, size, last, 0, 0};
+  if (breaks > 1 || size >= ((int64_t)1 << 31)) return {false, size, 0, 0, 0};
+  int64_t inner = 1;
+  for (size_t i = bpos + 1; i < order.size(); ++i) inner *= d.dim[l.find(order[i])];
+  return {true, size, last, inner, st[l.find(order[bpos])]};
+}
+
+static IdxMap make_map(const View2& v) {
+  IdxMap m;
+  if (v.inner == 0) return m;
+  m.D = (uint32_t)v.inner;
+  m.so = (uint32_t)v.ostride;
+  uint32_t sh = 0;
+  while ((1ull << sh) < (uint64_t)v.inner) ++sh;
+  m.sh = sh;
+  m.mag = (uint32_t)(((1ull << 32) * ((1ull << sh) - (uint64_t)v.inner)) / (uint64_t)v.inner + 1);
+  return m;
 }
 
 static std::string filter(const std::string& src, const std::string& keep) {
@@ -771,30 +871,98 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
     return P;
   }
 
+  // no summed index of extent above one: an elementwise product in the
+  // output's order, broadcast through zero strides (no packs, no temporary)
+  {
+    int64_t kx = 1;
+    for (char c : ki) kx *= dA.dim[la.find(c)];
+    if (kx == 1) {
+      auto sa = row_major_strides(dA), sb = row_major_strides(dB), so = row_major_strides(dO);
+      PermArgs& p = P.pc;
+      p = PermArgs{};
+      p.nd = (int)lo.size();
+      p.nin = 2;
+      p.mul = 1;
+      p.in[0] = pA;
+      p.in[1] = pB;
+      p.coef[0] = op.alpha;
+      p.out = pO;
+      p.addend = pC0;
+      p.beta = op.beta;
+      int64_t total = 1;
+      for (int i = 0; i < p.nd; ++i) {
+        const char c = lo[i];
+        p.dim[i] = dO.dim[i];
+        p.ostr[i] = so[i];
+        p.istr[0][i] = la.find(c) != std::string::npos ? sa[la.find(c)] : 0;
+        p.istr[1][i] = lb.find(c) != std::string::npos ? sb[lb.find(c)] : 0;
+        total *= dO.dim[i];
+      }
+      p.total = total;
+      P.kind = ContractKind::Outer;
+      P.g.M = total;
+      P.g.N = P.g.K = P.g.batch = 1;
+      return P;
+    }
+  }
+
   // choose fused orders; candidates from each operand's memory order
   std::vector<std::string> mcand = {filter(lo, mi), filter(la, mi)};
   std::vector<std::string> ncand = {filter(lo, ni), filter(lb, ni)};
   std::vector<std::string> kcand = {filter(la, ki), filter(lb, ki)};
   std::string bord = filter(lo, bat);
-  int64_t best = -1;
+  // Each candidate order is costed in time: the matrix-core kernel (slower
+  // per flop when it reads some group as two runs, from the index
+  // arithmetic of every load) plus each pack or output temporary as one
+  // read and one write at HBM speed and a launch.  Degenerate shapes
+  // (memory-bound kernels) take single-run operands only.
+  int64_t Mx = 1, Nx = 1, Kx = 1, Bx = 1;
+  for (char c : mi) Mx *= dO.dim[lo.find(c)];
+  for (char c : ni) Nx *= dO.dim[lo.find(c)];
+  for (char c : ki) Kx *= dA.dim[la.find(c)];
+  for (char c : bat) Bx *= dO.dim[lo.find(c)];
+  const int64_t lim32 = (int64_t)1 << 31;
+  const bool two_ok = !(Bx == 1 && (Mx == 1 || Nx == 1)) && dA.size() < lim32 && dB.size() < lim32 &&
+                      dO.size() < lim32;
+  constexpr double GEMM_RATE = 30e12, TWO_PENALTY = 1.25, HBM_RATE = 3e12, LAUNCH_S = 4e-6;
+  const double gemm_s = 2.0 * Mx * Nx * Kx * Bx / GEMM_RATE;
+  auto move_s = [&](int64_t elems) { return 16.0 * elems / HBM_RATE + LAUNCH_S; };
+  bool two = false;
+  auto view = [&](const std::string& l, const TensorDesc& d, const std::string& order) {
+    if (two) return fuse2(l, d, order);
+    View v = fuse(l, d, order);
+    return View2{v.ok, v.size, v.stride, 0, 0};
+  };
+  double best = -1;
+  bool best_two = false;
   std::string bm, bn, bk;
-  for (auto& m : mcand)
-    for (auto& n : ncand)
-      for (auto& k : kcand) {
-        int64_t cost = 0;
-        auto okA = fuse(la, dA, m).ok && fuse(la, dA, k).ok && fuse(la, dA, bord).ok;
-        auto okB = fuse(lb, dB, k).ok && fuse(lb, dB, n).ok && fuse(lb, dB, bord).ok;
-        auto okC = fuse(lo, dO, m).ok && fuse(lo, dO, n).ok && fuse(lo, dO, bord).ok;
-        if (!okA) cost += dA.size();
-        if (!okB) cost += dB.size();
-        if (!okC) cost += 2 * dO.size();
-        if (best < 0 || cost < best) {
-          best = cost;
-          bm = m;
-          bn = n;
-          bk = k;
+  for (int mode = 0; mode < (two_ok ? 2 : 1); ++mode) {
+    two = mode == 1;
+    for (auto& m : mcand)
+      for (auto& n : ncand)
+        for (auto& k : kcand) {
+          View2 am = view(la, dA, m), ak = view(la, dA, k), bk_ = view(lb, dB, k), bn_ = view(lb, dB, n);
+          View2 cm = view(lo, dO, m), cn = view(lo, dO, n);
+          const bool okA = am.ok && ak.ok && fuse(la, dA, bord).ok;
+          const bool okB = bk_.ok && bn_.ok && fuse(lb, dB, bord).ok;
+          const bool okC = cm.ok && cn.ok && fuse(lo, dO, bord).ok;
+          const bool any_two = (okA && (am.inner || ak.inner)) || (okB && (bk_.inner || bn_.inner)) ||
+                               (okC && (cm.inner || cn.inner));
+          if (two && !any_two) continue;  // the single-run pass has this one
+          double cost = gemm_s * (any_two ? TWO_PENALTY : 1.0);
+          if (!okA) cost += move_s(dA.size());
+          if (!okB) cost += move_s(dB.size());
+          if (!okC) cost += move_s(dO.size());
+          if (best < 0 || cost < best) {
+            best = cost;
+            best_two = two;
+            bm = m;
+            bn = n;
+            bk = k;
+          }
         }
-      }
+  }
+  two = best_two;
   int64_t M = 1, N = 1, K = 1, Bt = 1;
   for (char c : bm) M *= dO.dim[lo.find(c)];
   for (char c : bn) N *= dO.dim[lo.find(c)];
@@ -810,12 +978,15 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
   int64_t sc = 0;
   // A
   {
-    View vm = fuse(la, dA, bm), vk = fuse(la, dA, bk), vb = fuse(la, dA, bord);
+    View2 vm = view(la, dA, bm), vk = view(la, dA, bk);
+    View vb = fuse(la, dA, bord);
     if (vm.ok && vk.ok && vb.ok) {
       G.A = pA;
       G.sAm = vm.stride;
       G.sAk = vk.stride;
       G.sAb = vb.stride;
+      G.mAm = make_map(vm);
+      G.mAk = make_map(vk);
     } else {
       P.packA = true;
       P.pa = pack_args(dA, la, bord + bm + bk, pA, scratch + sc);
@@ -828,12 +999,15 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
   }
   // B
   {
-    View vk = fuse(lb, dB, bk), vn = fuse(lb, dB, bn), vb = fuse(lb, dB, bord);
+    View2 vk = view(lb, dB, bk), vn = view(lb, dB, bn);
+    View vb = fuse(lb, dB, bord);
     if (vk.ok && vn.ok && vb.ok) {
       G.B = pB;
       G.sBk = vk.stride;
       G.sBn = vn.stride;
       G.sBb = vb.stride;
+      G.mBk = make_map(vk);
+      G.mBn = make_map(vn);
     } else {
       P.packB = true;
       P.pb = pack_args(dB, lb, bord + bk + bn, pB, scratch + sc);
@@ -846,13 +1020,16 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
   }
   // C
   {
-    View vm = fuse(lo, dO, bm), vn = fuse(lo, dO, bn), vb = fuse(lo, dO, bord);
+    View2 vm = view(lo, dO, bm), vn = view(lo, dO, bn);
+    View vb = fuse(lo, dO, bord);
     if (vm.ok && vn.ok && vb.ok) {
       G.C = pO;
       G.Cin = pC0;
       G.sCm = vm.stride;
       G.sCn = vn.stride;
       G.sCb = vb.stride;
+      G.mCm = make_map(vm);
+      G.mCn = make_map(vn);
     } else {
       P.tmpC = true;
       double* tmp = scratch + sc;
@@ -887,12 +1064,14 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
       p.total = total;
     }
   }
-  // degenerate shapes are memory-bound: no matrix cores
-  if (K == 1) {
-    P.kind = ContractKind::Outer;
-    P.scratch = sc;
-    return P;
+  G.two = G.mAm.D || G.mAk.D || G.mBk.D || G.mBn.D || G.mCm.D || G.mCn.D;
+  if (G.two) {
+    // the two-run kernel takes every group through the same branch-free
+    // arithmetic: a single run is a first run of 2^31 (quotient 0)
+    for (IdxMap* m : {&G.mAm, &G.mAk, &G.mBk, &G.mBn, &G.mCm, &G.mCn})
+      if (m->D == 0) *m = IdxMap{1u << 31, 0, 1, 31};
   }
+  // degenerate shapes are memory-bound: no matrix cores
   if (Bt == 1 && (N == 1 || M == 1)) {
     GemvArgs& v = P.gv;
     v = GemvArgs{};
@@ -986,17 +1165,11 @@ Executor::~Executor() {
   }
 }
 
-void Executor::account(double ms, double flops, const std::array<int64_t, 5>& shape, bool f32) {
-  if (f32) {
-    f32_ms += ms;
-    f32_flops += flops;
-    ++f32_launches;
-    return;
-  }
-  gemm_ms += ms;
-  gemm_flops += flops;
-  ++gemm_launches;
-  ShapeStat& st = shapes_[shape];
+void Executor::account(double ms, double flops, const std::array<int64_t, 5>& shape, int kid) {
+  kernel_ms[kid] += ms;
+  kernel_flops[kid] += flops;
+  ++kernel_launches[kid];
+  ShapeStat& st = shapes_[{shape[0], shape[1], shape[2], shape[3], shape[4], kid}];
   st.n += 1;
   st.ms += ms;
   st.flops += flops;
@@ -1008,7 +1181,7 @@ void Executor::set_profile(bool on) {
     for (auto& e : ev_) check(hipEventCreate(&e), "event create");
     ev_flops_.resize(4096);
     ev_shape_.resize(4096);
-    ev_f32_.resize(4096);
+    ev_kid_.resize(4096);
   }
   if (!on) flush_profile();
   prof_ = on;
@@ -1020,7 +1193,7 @@ void Executor::flush_profile() {
   for (size_t i = 0; i < nev_; ++i) {
     float ms = 0;
     check(hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]), "event elapsed");
-    account(ms, ev_flops_[i], ev_shape_[i], ev_f32_[i] != 0);
+    account(ms, ev_flops_[i], ev_shape_[i], ev_kid_[i]);
   }
   nev_ = 0;
 }
@@ -1039,14 +1212,14 @@ void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32) {
     launch_gemm_reduce(g, s);
     cap_->flops.push_back(2.0 * g.M * g.N * g.K * g.batch);
     cap_->shape.push_back({g.M, g.N, g.K, g.batch, g.splits});
-    cap_->f32.push_back(f32 ? 1 : 0);
+    cap_->kid.push_back((char)gemm_kernel_id(g, f32));
     return;
   }
   if (nev_ == ev_flops_.size()) flush_profile();
   // the events bracket the MFMA kernel alone (a split-K reduction follows)
   check(hipEventRecord(ev_[2 * nev_], s), "event record");
   launch_gemm_main(g, s, f32);
-  ev_f32_[nev_] = f32 ? 1 : 0;
+  ev_kid_[nev_] = (char)gemm_kernel_id(g, f32);
   check(hipEventRecord(ev_[2 * nev_ + 1], s), "event record");
   launch_gemm_reduce(g, s);
   ev_flops_[nev_] = 2.0 * g.M * g.N * g.K * g.batch;
@@ -1055,16 +1228,21 @@ void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32) {
 }
 
 void Executor::shape_report(FILE* f, int top) const {
-  std::vector<std::pair<std::array<int64_t, 5>, ShapeStat>> v(shapes_.begin(), shapes_.end());
+  static const char* names[4] = {"f64", "f64/two", "f32", "f32/two"};
+  std::vector<std::pair<std::array<int64_t, 6>, ShapeStat>> v(shapes_.begin(), shapes_.end());
   std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
-  std::fprintf(f, "gemm shapes by time (M N K batch splits: launches, ms, TFLOP/s)\n");
+  std::fprintf(f, "gemm shapes by time (M N K batch splits kernel: launches, ms, TFLOP/s)\n");
   for (int i = 0; i < (int)v.size() && i < top; ++i) {
     const auto& k = v[i].first;
     const auto& st = v[i].second;
-    std::fprintf(f, "  %7lld %7lld %7lld %4lld %3lld: %9lld %10.1f %6.2f\n", (long long)k[0], (long long)k[1],
-                 (long long)k[2], (long long)k[3], (long long)k[4], (long long)st.n, st.ms,
+    std::fprintf(f, "  %7lld %7lld %7lld %4lld %3lld %-7s: %9lld %10.1f %6.2f\n", (long long)k[0], (long long)k[1],
+                 (long long)k[2], (long long)k[3], (long long)k[4], names[k[5]], (long long)st.n, st.ms,
                  st.ms > 0 ? st.flops / (st.ms * 1e9) : 0.0);
   }
+  for (int q = 0; q < 4; ++q)
+    if (kernel_launches[q])
+      std::fprintf(f, "  kernel %-7s: %lld launches, %.1f ms, %.2f TFLOP/s\n", names[q], (long long)kernel_launches[q],
+                   kernel_ms[q], kernel_flops[q] / (kernel_ms[q] * 1e9));
 }
 
 double Executor::flops(const std::vector<int>& list) const {
@@ -1115,7 +1293,7 @@ void Executor::run(const std::vector<int>& list, hipStream_t s) {
     for (size_t i = 0; i < c.flops.size(); ++i) {
       float ms = 0;
       check(hipEventElapsedTime(&ms, c.ev[2 * i], c.ev[2 * i + 1]), "event elapsed");
-      account(ms, c.flops[i], c.shape[i], c.f32[i] != 0);
+      account(ms, c.flops[i], c.shape[i], c.kid[i]);
     }
   }
 }
@@ -1131,8 +1309,7 @@ void Executor::run_op(int k, hipStream_t s) {
       if (p.dot) {
         launch_dot(p.g.A, p.g.B, p.g.K, p.g.alpha, p.g.Cin, p.g.beta, p.g.C, partials_, s);
       } else if (p.kind == ContractKind::Outer) {
-        launch_outer(p.g, s);
-        if (p.tmpC) launch_perm(p.pc, s);
+        launch_perm(p.pc, s);
       } else if (p.kind == ContractKind::Gemv) {
         launch_gemv(p.gv, s);
         if (p.tmpC) launch_perm(p.pc, s);

@@ -12,8 +12,17 @@
 
 namespace scc {
 
+// Address of index x of a fused index group spanning two runs of a tensor's
+// dimensions: (x / D) * so + (x % D) * s_inner (D = 0: one run, x * s_inner).
+// mag, sh: 32-bit magic-number division by D.
+struct IdxMap {
+  uint32_t D = 0, so = 0, mag = 0, sh = 0;
+};
+
 // C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] + beta * Cin[b][m][n]
-// with arbitrary element strides (one stride of each operand is normally 1).
+// with arbitrary element strides (one stride of each operand is normally 1);
+// the m, n and k groups of each operand may span two runs (IdxMap, inner
+// strides sAm, sAk, sBk, sBn, sCm, sCn).
 struct GemmArgs {
   int64_t M, N, K, batch;
   double alpha, beta;
@@ -29,6 +38,10 @@ struct GemmArgs {
   // in a fixed order into C (+ beta Cin).
   int64_t splits = 1, kchunk = 0;
   double* P = nullptr;
+  IdxMap mAm, mAk, mBk, mBn, mCm, mCn;
+  // some group spans two runs: the kernel takes 32-bit offsets (every
+  // operand of fewer than 2^31 elements)
+  bool two = false;
 };
 
 // out[idx] = sum_i coef_i * in_i[idx . istr_i] + beta * addend[idx . ostr]
@@ -45,11 +58,17 @@ struct PermArgs {
   const double* addend;
   double beta;
   int64_t total;
+  // mul: out = coef[0] * in[0] * in[1] (+ beta * addend), two inputs
+  int mul;
 };
 
 void launch_gemm(const GemmArgs& a, hipStream_t s);
 // the MFMA kernel alone, and the split-K reduction that follows it
 void launch_gemm_main(const GemmArgs& a, hipStream_t s, bool f32 = false);
+// the GEMM kernels: FP64 or FP32 products, operand groups of one run each or
+// of up to two runs
+enum GemmKernel { GEMM_F64 = 0, GEMM_F64_TWO = 1, GEMM_F32 = 2, GEMM_F32_TWO = 3 };
+inline int gemm_kernel_id(const GemmArgs& a, bool f32) { return (f32 ? 2 : 0) + (a.two ? 1 : 0); }
 void launch_gemm_reduce(const GemmArgs& a, hipStream_t s);
 // y[i] += sum_j coef[j] X[j][i] over X [k][n] (coef: device, k entries)
 void launch_combine(const double* X, int k, int64_t n, const double* coef, double* y, hipStream_t s);
@@ -90,7 +109,6 @@ struct GemvArgs {
 
 void launch_gemv(const GemvArgs& g, hipStream_t s);
 // K == 1: C[b][m][n] = alpha A[b][m] B[b][n] + beta Cin[b][m][n]
-void launch_outer(const GemmArgs& g, hipStream_t s);
 
 enum class ContractKind { Mfma, Dot, Gemv, Outer };
 
@@ -116,12 +134,12 @@ class Executor {
   double flops(const std::vector<int>& op_list) const;
   // GEMM kernel timing with HIP events (off by default)
   void set_profile(bool on);
+  bool profiling() const { return prof_; }
   void flush_profile();
-  // FP64 kernel totals; FP32-product kernel totals (reduced-precision mode)
-  double gemm_ms = 0.0, gemm_flops = 0.0;
-  int64_t gemm_launches = 0;
-  double f32_ms = 0.0, f32_flops = 0.0;
-  int64_t f32_launches = 0;
+  // timed totals per GEMM kernel (GemmKernel): milliseconds, algorithmic
+  // flops (2 M N K per launch), launches
+  double kernel_ms[4] = {}, kernel_flops[4] = {};
+  int64_t kernel_launches[4] = {};
   // reduced precision: dense contractions (M, N, K >= 64) take FP32 products
   void set_lowp(bool on) { lowp_ = on; }
   bool lowp() const { return lowp_; }
@@ -148,12 +166,12 @@ class Executor {
     std::vector<hipEvent_t> ev;
     std::vector<double> flops;
     std::vector<std::array<int64_t, 5>> shape;
-    std::vector<char> f32;
+    std::vector<char> kid;
   };
   std::map<std::array<int64_t, 3>, Captured> graphs_cache_;
   Captured* cap_ = nullptr;  // set while a graph is being captured
-  void account(double ms, double flops, const std::array<int64_t, 5>& shape, bool f32);
-  std::vector<char> ev_f32_;
+  void account(double ms, double flops, const std::array<int64_t, 5>& shape, int kid);
+  std::vector<char> ev_kid_;
   std::vector<hipEvent_t> ev_;
   std::vector<double> ev_flops_;
   std::vector<std::array<int64_t, 5>> ev_shape_;
@@ -161,7 +179,7 @@ class Executor {
     int64_t n = 0;
     double ms = 0.0, flops = 0.0;
   };
-  std::map<std::array<int64_t, 5>, ShapeStat> shapes_;
+  std::map<std::array<int64_t, 6>, ShapeStat> shapes_;
   size_t nev_ = 0;
   void run_op(int k, hipStream_t s);
   void timed_gemm(const GemmArgs& g, hipStream_t s, bool f32);

@@ -2072,15 +2072,16 @@ int scc_get(scc_ctx* c, int field, int k, double* out) {
   });
 }
 
-int scc_profile(scc_ctx* c, int enable, double* gemm_ms, double* gemm_flops, long long* gemm_launches) {
-  if (!c) return SCC_EINVAL;
+int scc_profile(scc_ctx* c, int enable, int kernel, double* gemm_ms, double* gemm_flops, long long* gemm_launches) {
+  if (!c || kernel < 0 || kernel > 3) return SCC_EINVAL;
   return guarded(c, nullptr, [&]() -> int {
+    const bool was_on = c->ex->profiling();
     c->ex->flush_profile();
     c->ex->set_profile(enable != 0);
-    if (!enable && c->opt.verbose) c->ex->shape_report(stderr, 25);
-    if (gemm_ms) *gemm_ms = c->ex->gemm_ms;
-    if (gemm_flops) *gemm_flops = c->ex->gemm_flops;
-    if (gemm_launches) *gemm_launches = (long long)c->ex->gemm_launches;
+    if (!enable && was_on && c->opt.verbose) c->ex->shape_report(stderr, 25);
+    if (gemm_ms) *gemm_ms = c->ex->kernel_ms[kernel];
+    if (gemm_flops) *gemm_flops = c->ex->kernel_flops[kernel];
+    if (gemm_launches) *gemm_launches = (long long)c->ex->kernel_launches[kernel];
     return SCC_OK;
   });
 }
