@@ -246,13 +246,29 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_two_kernel(GemmArgs 
     gemm_body<16, true, true>(a, As, Bs);
 }
 
+// sum_{s < n} p[s * stride] in the order s = 0, 1, ...: the loads are issued
+// in batches of eight ahead of the additions (latency, not bandwidth, bounds
+// a serial chain of loads)
+__device__ __forceinline__ double ordered_sum(const double* p, int64_t n, int64_t stride) {
+  double v = 0.0;
+  int64_t s = 0;
+  for (; s + 8 <= n; s += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[(s + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; s < n; ++s) v += p[s * stride];
+  return v;
+}
+
 __global__ void splitk_reduce_kernel(GemmArgs a) {
   const int64_t mn = a.M * a.N;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mn; i += stride) {
     const int64_t row = i / a.N, col = i % a.N;
-    double v = 0.0;
-    for (int64_t s = 0; s < a.splits; ++s) v += a.P[s * mn + i];
+    double v = ordered_sum(a.P + i, a.splits, mn);
     const int64_t o = imap(row, a.mCm, a.sCm) + imap(col, a.mCn, a.sCn);
     if (a.Cin) v += a.beta * a.Cin[o];
     a.C[o] = v;
@@ -302,7 +318,18 @@ __global__ __launch_bounds__(RED_THREADS) void dot_partial_kernel(const double* 
                                                                   double* partials) {
   double v = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) v += x[i] * y[i];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = x[i + u * stride];
+      b[u] = y[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v += a[u] * b[u];
+  }
+  for (; i < n; i += stride) v += x[i] * y[i];
   v = block_sum(v);
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
@@ -352,19 +379,30 @@ __global__ __launch_bounds__(RED_THREADS) void deriv_contract_kernel(const doubl
   const double* l = dL + (int64_t)k * nl;
   double v = 0.0;
   const int64_t stride = (int64_t)chunks * blockDim.x;
-  for (int64_t i = (int64_t)c * blockDim.x + threadIdx.x; i < nh; i += stride) v += h[i] * D1[i];
-  for (int64_t i = (int64_t)c * blockDim.x + threadIdx.x; i < nl; i += stride) v += l[i] * Z[i];
+  // four loads of each operand in flight per batch; same summation order
+  auto dot = [&](const double* x, const double* y, int64_t n) {
+    int64_t i = (int64_t)c * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = x[i + u * stride];
+        b[u] = y[i + u * stride];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v += a[u] * b[u];
+    }
+    for (; i < n; i += stride) v += x[i] * y[i];
+  };
+  dot(h, D1, nh);
+  dot(l, Z, nl);
   v = block_sum(v);
   if (threadIdx.x == 0) partials[(int64_t)k * chunks + c] = v;
 }
 
 __global__ void deriv_final_kernel(const double* partials, int chunks, int ncoord, double* grad) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < ncoord) {
-    double v = 0.0;
-    for (int c = 0; c < chunks; ++c) v += partials[(int64_t)k * chunks + c];
-    grad[k] = v;
-  }
+  if (k < ncoord) grad[k] = ordered_sum(partials + (int64_t)k * chunks, chunks, 1);
 }
 
 static void check(hipError_t e, const char* what) {
@@ -407,7 +445,15 @@ __global__ void combine_kernel(const double* __restrict__ X, int k, int64_t n, c
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double acc = y[i];
-    for (int j = 0; j < k; ++j) acc += coef[j] * X[(int64_t)j * n + i];
+    int j = 0;
+    for (; j + 8 <= k; j += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = X[(int64_t)(j + u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += coef[j + u] * t[u];
+    }
+    for (; j < k; ++j) acc += coef[j] * X[(int64_t)j * n + i];
     y[i] = acc;
   }
 }
@@ -422,7 +468,18 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(GemvArgs g) {
   const int64_t ke = g.splits > 1 ? min(g.K, kb + g.kchunk) : g.K;
   const double* m = g.Mt + row * g.sr;
   double acc = 0.0;
-  for (int64_t k = kb + lane; k < ke; k += 64) acc += m[k * g.sk] * g.x[k * g.sx];
+  int64_t k = kb + lane;
+  for (; k + 3 * 64 < ke; k += 4 * 64) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = m[(k + 64 * u) * g.sk];
+      b[u] = g.x[(k + 64 * u) * g.sx];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += a[u] * b[u];
+  }
+  for (; k < ke; k += 64) acc += m[k * g.sk] * g.x[k * g.sx];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) {
     if (g.splits > 1) {
@@ -444,7 +501,18 @@ __global__ __launch_bounds__(256) void gemv_cols_kernel(GemvArgs g) {
   const int64_t ke = g.splits > 1 ? min(g.K, kb + g.kchunk) : g.K;
   const double* m = g.Mt + row * g.sr;
   double acc = 0.0;
-  for (int64_t k = kb; k < ke; ++k) acc += m[k * g.sk] * g.x[k * g.sx];
+  int64_t k = kb;
+  for (; k + 4 <= ke; k += 4) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = m[(k + u) * g.sk];
+      b[u] = g.x[(k + u) * g.sx];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += a[u] * b[u];
+  }
+  for (; k < ke; ++k) acc += m[k * g.sk] * g.x[k * g.sx];
   if (g.splits > 1) {
     g.P[split * g.R + row] = acc;
   } else {
@@ -457,8 +525,7 @@ __global__ __launch_bounds__(256) void gemv_cols_kernel(GemvArgs g) {
 __global__ void gemv_reduce_kernel(GemvArgs g) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < g.R; r += stride) {
-    double v = 0.0;
-    for (int64_t s = 0; s < g.splits; ++s) v += g.P[s * g.R + r];
+    double v = ordered_sum(g.P + r, g.splits, g.R);
     v *= g.alpha;
     if (g.yin) v += g.beta * g.yin[r * g.sy];
     g.y[r * g.sy] = v;
@@ -924,7 +991,7 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
   const int64_t lim32 = (int64_t)1 << 31;
   const bool two_ok = !(Bx == 1 && (Mx == 1 || Nx == 1)) && dA.size() < lim32 && dB.size() < lim32 &&
                       dO.size() < lim32;
-  constexpr double GEMM_RATE = 30e12, TWO_PENALTY = 1.25, HBM_RATE = 3e12, LAUNCH_S = 4e-6;
+  constexpr double GEMM_RATE = 30e12, TWO_PENALTY = 1.07, HBM_RATE = 3e12, LAUNCH_S = 4e-6;
   const double gemm_s = 2.0 * Mx * Nx * Kx * Bx / GEMM_RATE;
   auto move_s = [&](int64_t elems) { return 16.0 * elems / HBM_RATE + LAUNCH_S; };
   bool two = false;

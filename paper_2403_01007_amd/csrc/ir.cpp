@@ -235,58 +235,82 @@ std::map<int, int> Graph::vjp(int begin, int end, const std::map<int, int>& seed
       d = dep[op.a];
     if (d) dep[op.out] = 1;
   }
-  std::map<int, std::vector<int>> contrib;
+  // Contributions to each tensor's adjoint are kept as terms (coefficient,
+  // tensor, index map) and summed by one lincomb when the adjoint is needed
+  // as a whole; a lone scaled or permuted term is passed on to the consuming
+  // contraction or lincomb without being copied.
+  std::map<int, std::vector<Term>> contrib;
+  auto def = [&](int id) { return default_labels(t[id].nd); };
   for (auto& kv : seeds)
-    if (!t[kv.second].zero) contrib[kv.first].push_back(kv.second);
-  auto total = [&](int id) -> int {
+    if (!t[kv.second].zero) contrib[kv.first].push_back({1.0, kv.second, def(kv.second)});
+  auto materialize = [&](int id) -> int {
     auto it = contrib.find(id);
     if (it == contrib.end() || it->second.empty()) return -1;
-    if (it->second.size() == 1) return it->second[0];
-    std::string l = default_labels(t[id].nd);
-    std::vector<Term> terms;
-    for (int c : it->second) terms.push_back({1.0, c, l});
-    int s = lincomb(l, terms);
-    it->second.assign(1, s);
+    const std::string l = def(id);
+    if (it->second.size() == 1 && it->second[0].coef == 1.0 && it->second[0].labels == l) return it->second[0].id;
+    int s = lincomb(l, it->second);
+    it->second.assign(1, Term{1.0, s, l});
     return s;
+  };
+  auto term = [&](int id, Term& out) -> bool {
+    auto it = contrib.find(id);
+    if (it == contrib.end() || it->second.empty()) return false;
+    if (it->second.size() > 1) materialize(id);
+    out = it->second[0];
+    return !t[out.id].zero;
   };
   for (int k = end - 1; k >= begin; --k) {
     const Op op = ops[k];
     if (!dep[op.out]) continue;
-    int g = total(op.out);
-    if (g < 0 || t[g].zero) continue;
     switch (op.kind) {
       case OpKind::Contract: {
+        Term g;
+        if (!term(op.out, g)) break;
+        // letters of the term's dimensions in the op's index names
+        std::string lx;
+        for (char c : g.labels) lx += op.lo[c - 'a'];
         if (dep[op.a]) {
-          int r = contract(op.lo + "," + op.lb + "->" + op.la, g, op.b, op.alpha);
-          if (!t[r].zero) contrib[op.a].push_back(r);
+          int r = contract(lx + "," + op.lb + "->" + op.la, g.id, op.b, op.alpha * g.coef);
+          if (!t[r].zero) contrib[op.a].push_back({1.0, r, def(op.a)});
         }
         if (dep[op.b]) {
-          int r = contract(op.la + "," + op.lo + "->" + op.lb, op.a, g, op.alpha);
-          if (!t[r].zero) contrib[op.b].push_back(r);
+          int r = contract(op.la + "," + lx + "->" + op.lb, op.a, g.id, op.alpha * g.coef);
+          if (!t[r].zero) contrib[op.b].push_back({1.0, r, def(op.b)});
         }
-        if (op.c0 >= 0 && dep[op.c0]) contrib[op.c0].push_back(op.beta == 1.0 ? g : scale(g, op.beta));
+        if (op.c0 >= 0 && dep[op.c0]) contrib[op.c0].push_back({op.beta * g.coef, g.id, g.labels});
         break;
       }
-      case OpKind::Lincomb:
-        for (size_t i = 0; i < op.ins.size(); ++i)
-          if (dep[op.ins[i]]) contrib[op.ins[i]].push_back(lincomb(op.lin[i], {{op.coef[i], g, op.lo}}));
+      case OpKind::Lincomb: {
+        Term g;
+        if (!term(op.out, g)) break;
+        for (size_t i = 0; i < op.ins.size(); ++i) {
+          if (!dep[op.ins[i]]) continue;
+          std::string l;
+          for (char c : g.labels) l += (char)('a' + op.lin[i].find(op.lo[c - 'a']));
+          contrib[op.ins[i]].push_back({op.coef[i] * g.coef, g.id, l});
+        }
         break;
+      }
       case OpKind::Slice:
         if (dep[op.a]) {
+          int g = materialize(op.out);
+          if (g < 0 || t[g].zero) break;
           std::vector<int64_t> off(op.off.begin(), op.off.begin() + t[op.a].nd);
-          contrib[op.a].push_back(embed(g, off, dims(op.a)));
+          contrib[op.a].push_back({1.0, embed(g, off, dims(op.a)), def(op.a)});
         }
         break;
       case OpKind::Embed:
         if (dep[op.a]) {
+          int g = materialize(op.out);
+          if (g < 0 || t[g].zero) break;
           std::vector<int64_t> off(op.off.begin(), op.off.begin() + t[op.a].nd);
-          contrib[op.a].push_back(slice(g, off, dims(op.a)));
+          contrib[op.a].push_back({1.0, slice(g, off, dims(op.a)), def(op.a)});
         }
         break;
     }
   }
   std::map<int, int> out;
-  for (int w : wanted) out[w] = total(w);
+  for (int w : wanted) out[w] = materialize(w);
   return out;
 }
 
