@@ -12,8 +12,9 @@ ERRORS = {0: "SCC_OK", -1: "SCC_EINVAL", -2: "SCC_ESTATE", -3: "SCC_ENOCONV", -4
           -5: "SCC_ESINGULAR", -6: "SCC_EDEVICE", -7: "SCC_ENOMEM"}
 FIELD_T, FIELD_R, FIELD_L, FIELD_E0, FIELD_OMEGA = 0, 1, 2, 3, 4
 # GEMM kernels whose launches scc_profile totals
-GEMM_F64, GEMM_F64_TWO, GEMM_F32, GEMM_F32_TWO = 0, 1, 2, 3
-GEMM_KERNEL_NAMES = ["gemm_f64_kernel", "gemm_f64_two_kernel", "gemm_f32acc_kernel", "gemm_f32acc_two_kernel"]
+GEMM_F64, GEMM_F64_TWO, GEMM_F32, GEMM_F32_TWO, GEMM_F64_MULTI, GEMM_F32_MULTI = 0, 1, 2, 3, 4, 5
+GEMM_KERNEL_NAMES = ["gemm_f64_kernel", "gemm_f64_two_kernel", "gemm_f32acc_kernel", "gemm_f32acc_two_kernel",
+                     "gemm_f64_multi_kernel", "gemm_f32acc_multi_kernel"]
 
 EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_last_error",
                     "scc_set_hamiltonian", "scc_set_hamiltonian_fixed_basis", "scc_ground", "scc_excited", "scc_multipliers",

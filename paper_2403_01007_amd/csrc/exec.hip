@@ -263,6 +263,197 @@ __device__ __forceinline__ double ordered_sum(const double* p, int64_t n, int64_
   return v;
 }
 
+// Multi-segment GEMM: the products of every segment accumulate in the same
+// registers (one pass over the output), each segment staged through LDS with
+// its own operand layout and its coefficient applied on the way in.
+template <int BKT, bool F32>
+__device__ __forceinline__ void gemm_multi_body(const GemmMulti& G,
+                                                typename std::conditional<F32, float, double>::type (*As)[BM + 1],
+                                                typename std::conditional<F32, float, double>::type (*Bs)[BN + 1]) {
+  typedef typename std::conditional<F32, float, double>::type T;
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const GemmArgs& a = G.g;
+  const int64_t split = a.splits > 1 ? blockIdx.z : 0;
+  const int64_t bz = a.splits > 1 ? 0 : blockIdx.z;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const int64_t kbeg = a.splits > 1 ? split * a.kchunk : 0;
+  const int64_t kend = a.splits > 1 ? min(a.K, kbeg + a.kchunk) : a.K;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 32;
+  const int wn = (wave & 1) * 32;
+  constexpr int EA = BM * BKT / GEMM_THREADS, EB = BN * BKT / GEMM_THREADS;
+  v4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
+  // The slabs of all segments form one sequence; the loads of the next slab
+  // (possibly the first of the next segment) are in flight while the matrix
+  // cores work on the current one.
+  struct Cur {
+    const double* A;
+    const double* B;
+    int64_t le;
+    bool a_kfast, b_nfast;
+    double alpha;
+  } cur{};
+  int cs = 0;  // segment of the slab being loaded
+  uint32_t aoff[EA], boff[EB];
+  double ra[EA], rb[EB];
+  auto a_pos = [&](bool kfast, int e, int& mm, int& kk) {
+    const int idx = tid + e * GEMM_THREADS;
+    if (kfast) {
+      kk = idx % BKT;
+      mm = idx / BKT;
+    } else {
+      mm = idx % BM;
+      kk = idx / BM;
+    }
+  };
+  auto b_pos = [&](bool nfast, int e, int& nn, int& kk) {
+    const int idx = tid + e * GEMM_THREADS;
+    if (nfast) {
+      nn = idx % BN;
+      kk = idx / BN;
+    } else {
+      kk = idx % BKT;
+      nn = idx / BKT;
+    }
+  };
+  // first segment at or after sg with summed indices in this block's range
+  auto open_seg = [&](int sg, int64_t& lb) -> int {
+    for (; sg < G.nseg; ++sg) {
+      const GemmSeg& S = G.seg[sg];
+      lb = max(kbeg - S.k0, (int64_t)0);
+      const int64_t le = min(kend - S.k0, S.K);
+      if (lb >= le) continue;
+      cs = sg;
+      cur.A = S.A + bz * S.sAb;
+      cur.B = S.B + bz * S.sBb;
+      cur.le = le;
+      cur.a_kfast = (S.sAk == 1);
+      cur.b_nfast = (S.sBn == 1) || (S.sBk != 1);
+      cur.alpha = S.alpha;
+#pragma unroll
+      for (int e = 0; e < EA; ++e) {
+        int mm, kk;
+        a_pos(cur.a_kfast, e, mm, kk);
+        const int64_t gm = m0 + mm;
+        aoff[e] = gm < a.M ? imap32((uint32_t)gm, S.mAm, S.sAm) : 0u;
+      }
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        int nn, kk;
+        b_pos(cur.b_nfast, e, nn, kk);
+        const int64_t gn = n0 + nn;
+        boff[e] = gn < a.N ? imap32((uint32_t)gn, S.mBn, S.sBn) : 0u;
+      }
+      return sg;
+    }
+    return -1;
+  };
+  auto load = [&](int64_t k0) {
+    const GemmSeg& S = G.seg[cs];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      int mm, kk;
+      a_pos(cur.a_kfast, e, mm, kk);
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      ra[e] = (gm < a.M && gk < cur.le) ? cur.A[aoff[e] + imap32((uint32_t)gk, S.mAk, S.sAk)] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      int nn, kk;
+      b_pos(cur.b_nfast, e, nn, kk);
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      rb[e] = (gn < a.N && gk < cur.le) ? cur.B[boff[e] + imap32((uint32_t)gk, S.mBk, S.sBk)] : 0.0;
+    }
+  };
+  int64_t k0 = 0;
+  int sg = open_seg(0, k0);
+  if (sg >= 0) load(k0);
+  while (sg >= 0) {
+    // the registers hold slab k0 of segment sg
+    const bool kf = cur.a_kfast, nf = cur.b_nfast;
+    const double alpha = cur.alpha;
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      int mm, kk;
+      a_pos(kf, e, mm, kk);
+      As[kk][mm] = (T)(alpha * ra[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      int nn, kk;
+      b_pos(nf, e, nn, kk);
+      Bs[kk][nn] = (T)rb[e];
+    }
+    __syncthreads();
+    k0 += BKT;
+    if (k0 >= cur.le) sg = open_seg(sg + 1, k0);
+    if (sg >= 0) load(k0);
+#pragma unroll
+    for (int kk = 0; kk < BKT; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      T af[2], bf[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        af[t] = As[kr][wm + t * 16 + (lane & 15)];
+        bf[t] = Bs[kr][wn + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (F32)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  const bool part = a.splits > 1;
+  double* out = part ? a.P + split * a.M * a.N : a.C + bz * a.sCb;
+  const double* Cin = (part || !a.Cin) ? nullptr : a.Cin + bz * a.sCb;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = F32 ? (lane >> 4) * 4 + r : r * 4 + (lane >> 4);
+        const int64_t row = m0 + wm + i * 16 + rr;
+        const int64_t col = n0 + wn + j * 16 + (lane & 15);
+        if (row < a.M && col < a.N) {
+          double v = (double)acc[i][j][r];
+          const int64_t o = part ? row * a.N + col
+                                 : (int64_t)(imap32((uint32_t)row, a.mCm, a.sCm) + imap32((uint32_t)col, a.mCn, a.sCn));
+          if (Cin) v += a.beta * Cin[o];
+          out[o] = v;
+        }
+      }
+}
+
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_multi_kernel(GemmMulti m) {
+  __shared__ double As[BKMAX][BM + 1];
+  __shared__ double Bs[BKMAX][BN + 1];
+  if (m.g.K >= 256 * m.nseg)
+    gemm_multi_body<32, false>(m, As, Bs);
+  else
+    gemm_multi_body<16, false>(m, As, Bs);
+}
+
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_multi_kernel(GemmMulti m) {
+  __shared__ float As[BKMAX][BM + 1];
+  __shared__ float Bs[BKMAX][BN + 1];
+  if (m.g.K >= 256 * m.nseg)
+    gemm_multi_body<32, true>(m, As, Bs);
+  else
+    gemm_multi_body<16, true>(m, As, Bs);
+}
+
 __global__ void splitk_reduce_kernel(GemmArgs a) {
   const int64_t mn = a.M * a.N;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -433,6 +624,21 @@ void launch_gemm_reduce(const GemmArgs& a, hipStream_t s) {
   if (a.splits <= 1 || a.M <= 0 || a.N <= 0) return;
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(a.M * a.N)), dim3(256), 0, s, a);
   check(hipGetLastError(), "split-K reduce launch");
+}
+
+void launch_gemm_multi(const GemmMulti& m, hipStream_t s, bool f32) {
+  const GemmArgs& a = m.g;
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return;
+  if (m.nseg < 1 || m.nseg > MAXSEG) throw std::runtime_error("bad multi-segment GEMM");
+  if (a.splits > 1 && (a.batch != 1 || !a.P || a.kchunk <= 0)) throw std::runtime_error("bad split-K plan");
+  dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((a.M + BM - 1) / BM),
+            (unsigned)(a.splits > 1 ? a.splits : a.batch));
+  if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm grid too large");
+  if (f32)
+    hipLaunchKernelGGL(gemm_f32acc_multi_kernel, grid, dim3(GEMM_THREADS), 0, s, m);
+  else
+    hipLaunchKernelGGL(gemm_f64_multi_kernel, grid, dim3(GEMM_THREADS), 0, s, m);
+  check(hipGetLastError(), "multi gemm launch");
 }
 
 void launch_gemm(const GemmArgs& a, hipStream_t s) {
@@ -894,7 +1100,210 @@ static PermArgs pack_args(const TensorDesc& d, const std::string& l, const std::
   return p;
 }
 
+// Plan of a contraction with several products (Op::segs): the output index
+// groups (batch, rows from the first operands, columns from the second) are
+// common; each product gets its own summed-index order, and an operand that
+// no order of up to two runs reads in place is packed.
+static ContractPlan plan_multi(const Graph& g, const Op& op, double* arena, double* scratch) {
+  ContractPlan P;
+  P.kind = ContractKind::Multi;
+  const TensorDesc& dO = g.t[op.out];
+  const std::string& lo = op.lo;
+  std::vector<Seg> ss = {Seg{op.a, op.b, op.la, op.lb, op.alpha}};
+  for (const Seg& x : op.segs) ss.push_back(x);
+  if ((int)ss.size() > MAXSEG) throw std::runtime_error("too many products in one contraction");
+  std::string bat, mi, ni;
+  for (char c : lo) {
+    const bool ia = ss[0].la.find(c) != std::string::npos, ib = ss[0].lb.find(c) != std::string::npos;
+    (ia && ib ? bat : ia ? mi : ni) += c;
+  }
+  for (const Seg& x : ss)
+    for (char c : lo) {
+      const bool ia = x.la.find(c) != std::string::npos, ib = x.lb.find(c) != std::string::npos;
+      const bool ok = (ia && ib) ? bat.find(c) != std::string::npos
+                                 : ia ? mi.find(c) != std::string::npos : ni.find(c) != std::string::npos;
+      if (!ok) throw std::runtime_error("products of one contraction split the output differently");
+    }
+  const std::string bord = filter(lo, bat);
+  int64_t M = 1, N = 1, Bt = 1;
+  for (char c : mi) M *= dO.dim[lo.find(c)];
+  for (char c : ni) N *= dO.dim[lo.find(c)];
+  for (char c : bord) Bt *= dO.dim[lo.find(c)];
+  constexpr double HBM_RATE = 3e12, LAUNCH_S = 4e-6;
+  auto move_s = [&](int64_t elems) { return 16.0 * elems / HBM_RATE + LAUNCH_S; };
+  auto kset = [&](const Seg& x) {
+    std::string k;
+    for (char c : x.la)
+      if (x.lb.find(c) != std::string::npos && lo.find(c) == std::string::npos) k += c;
+    return k;
+  };
+  // cost of one product for given row / column orders: best summed order
+  auto seg_cost = [&](const Seg& x, const std::string& m, const std::string& n, std::string* kbest) {
+    const TensorDesc& dA = g.t[x.a];
+    const TensorDesc& dB = g.t[x.b];
+    const std::string ki = kset(x);
+    double best = -1;
+    for (const std::string& k : {filter(x.la, ki), filter(x.lb, ki)}) {
+      const bool okA = fuse2(x.la, dA, m).ok && fuse2(x.la, dA, k).ok && fuse(x.la, dA, bord).ok;
+      const bool okB = fuse2(x.lb, dB, k).ok && fuse2(x.lb, dB, n).ok && fuse(x.lb, dB, bord).ok;
+      const double c = (okA ? 0.0 : move_s(dA.size())) + (okB ? 0.0 : move_s(dB.size()));
+      if (best < 0 || c < best) {
+        best = c;
+        if (kbest) *kbest = k;
+      }
+    }
+    return best;
+  };
+  std::string bm, bn;
+  double best = -1;
+  for (const std::string& m : {filter(lo, mi), filter(ss[0].la, mi)})
+    for (const std::string& n : {filter(lo, ni), filter(ss[0].lb, ni)}) {
+      double c = (fuse2(lo, dO, m).ok && fuse2(lo, dO, n).ok && fuse(lo, dO, bord).ok) ? 0.0 : move_s(dO.size());
+      for (const Seg& x : ss) c += seg_cost(x, m, n, nullptr);
+      if (best < 0 || c < best) {
+        best = c;
+        bm = m;
+        bn = n;
+      }
+    }
+  const double* pC0 = op.c0 >= 0 ? arena + g.t[op.c0].offset : nullptr;
+  double* pO = arena + dO.offset;
+  GemmArgs& G = P.g;
+  G.M = M;
+  G.N = N;
+  G.batch = Bt;
+  G.alpha = 1.0;
+  G.beta = op.beta;
+  G.two = true;
+  int64_t sc = 0, ktot = 0;
+  for (const Seg& x : ss) {
+    const TensorDesc& dA = g.t[x.a];
+    const TensorDesc& dB = g.t[x.b];
+    std::string bk;
+    seg_cost(x, bm, bn, &bk);
+    int64_t K = 1;
+    for (char c : bk) K *= dA.dim[x.la.find(c)];
+    GemmSeg q{};
+    q.K = K;
+    q.k0 = ktot;
+    q.alpha = x.alpha;
+    ktot += K;
+    const double* pA = arena + dA.offset;
+    const double* pB = arena + dB.offset;
+    View2 vm = fuse2(x.la, dA, bm), vk = fuse2(x.la, dA, bk);
+    View vb = fuse(x.la, dA, bord);
+    if (vm.ok && vk.ok && vb.ok) {
+      q.A = pA;
+      q.sAm = vm.stride;
+      q.sAk = vk.stride;
+      q.sAb = vb.stride;
+      q.mAm = make_map(vm);
+      q.mAk = make_map(vk);
+    } else {
+      P.spacks.push_back(pack_args(dA, x.la, bord + bm + bk, pA, scratch + sc));
+      q.A = scratch + sc;
+      q.sAk = 1;
+      q.sAm = K;
+      q.sAb = M * K;
+      sc += dA.size();
+    }
+    View2 wk = fuse2(x.lb, dB, bk), wn = fuse2(x.lb, dB, bn);
+    View wb = fuse(x.lb, dB, bord);
+    if (wk.ok && wn.ok && wb.ok) {
+      q.B = pB;
+      q.sBk = wk.stride;
+      q.sBn = wn.stride;
+      q.sBb = wb.stride;
+      q.mBk = make_map(wk);
+      q.mBn = make_map(wn);
+    } else {
+      P.spacks.push_back(pack_args(dB, x.lb, bord + bk + bn, pB, scratch + sc));
+      q.B = scratch + sc;
+      q.sBn = 1;
+      q.sBk = N;
+      q.sBb = K * N;
+      sc += dB.size();
+    }
+    P.segs.push_back(q);
+  }
+  G.K = ktot;
+  {
+    View2 vm = fuse2(lo, dO, bm), vn = fuse2(lo, dO, bn);
+    View vb = fuse(lo, dO, bord);
+    if (vm.ok && vn.ok && vb.ok) {
+      G.C = pO;
+      G.Cin = pC0;
+      G.sCm = vm.stride;
+      G.sCn = vn.stride;
+      G.sCb = vb.stride;
+      G.mCm = make_map(vm);
+      G.mCn = make_map(vn);
+    } else {
+      P.tmpC = true;
+      double* tmp = scratch + sc;
+      sc += dO.size();
+      G.C = tmp;
+      G.Cin = nullptr;
+      G.beta = 0.0;
+      G.sCn = 1;
+      G.sCm = N;
+      G.sCb = M * N;
+      const std::string tl = bord + bm + bn;
+      PermArgs& p = P.pc;
+      p = PermArgs{};
+      p.nd = (int)lo.size();
+      p.nin = 1;
+      p.in[0] = tmp;
+      p.coef[0] = 1.0;
+      p.out = pO;
+      p.addend = pC0;
+      p.beta = op.beta;
+      std::vector<int64_t> tst(tl.size(), 1);
+      for (int i = (int)tl.size() - 2; i >= 0; --i) tst[i] = tst[i + 1] * dO.dim[lo.find(tl[i + 1])];
+      auto ost = row_major_strides(dO);
+      int64_t total = 1;
+      for (int i = 0; i < p.nd; ++i) {
+        p.dim[i] = dO.dim[i];
+        p.ostr[i] = ost[i];
+        p.istr[0][i] = tst[tl.find(lo[i])];
+        total *= dO.dim[i];
+      }
+      p.total = total;
+    }
+  }
+  // every group through the branch-free two-run arithmetic
+  const IdxMap ident{1u << 31, 0, 1, 31};
+  for (IdxMap* m : {&G.mCm, &G.mCn})
+    if (m->D == 0) *m = ident;
+  for (GemmSeg& q : P.segs)
+    for (IdxMap* m : {&q.mAm, &q.mAk, &q.mBk, &q.mBn})
+      if (m->D == 0) *m = ident;
+  // split-K over the concatenated summed index when the tiles cannot fill the chip
+  {
+    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * Bt;
+    const int64_t target = 1024;
+    if (Bt == 1 && ktot >= 128 && tiles < target) {
+      int64_t sp = std::min<int64_t>((target + tiles - 1) / tiles, ktot / 64);
+      sp = std::min<int64_t>(sp, 1024);
+      if (sp > 1) {
+        int64_t kc = (ktot + sp - 1) / sp;
+        kc = (kc + BK - 1) / BK * BK;
+        sp = (ktot + kc - 1) / kc;
+        if (sp > 1) {
+          G.splits = sp;
+          G.kchunk = kc;
+          G.P = scratch + sc;
+          sc += sp * M * N;
+        }
+      }
+    }
+  }
+  P.scratch = sc;
+  return P;
+}
+
 ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* scratch) {
+  if (!op.segs.empty()) return plan_multi(g, op, arena, scratch);
   ContractPlan P;
   const TensorDesc& dA = g.t[op.a];
   const TensorDesc& dB = g.t[op.b];
@@ -1265,7 +1674,14 @@ void Executor::flush_profile() {
   nev_ = 0;
 }
 
-void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32) {
+void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32, const GemmMulti* multi) {
+  const int kid = multi ? (f32 ? GEMM_F32_MULTI : GEMM_F64_MULTI) : gemm_kernel_id(g, f32);
+  auto main = [&]() {
+    if (multi)
+      launch_gemm_multi(*multi, s, f32);
+    else
+      launch_gemm_main(g, s, f32);
+  };
   if (cap_) {
     // inside a graph capture: event pairs of the graph's own
     hipEvent_t e0, e1;
@@ -1274,19 +1690,19 @@ void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32) {
     cap_->ev.push_back(e0);
     cap_->ev.push_back(e1);
     check(hipEventRecord(e0, s), "event record");
-    launch_gemm_main(g, s, f32);
+    main();
     check(hipEventRecord(e1, s), "event record");
     launch_gemm_reduce(g, s);
     cap_->flops.push_back(2.0 * g.M * g.N * g.K * g.batch);
     cap_->shape.push_back({g.M, g.N, g.K, g.batch, g.splits});
-    cap_->kid.push_back((char)gemm_kernel_id(g, f32));
+    cap_->kid.push_back((char)kid);
     return;
   }
   if (nev_ == ev_flops_.size()) flush_profile();
   // the events bracket the MFMA kernel alone (a split-K reduction follows)
   check(hipEventRecord(ev_[2 * nev_], s), "event record");
-  launch_gemm_main(g, s, f32);
-  ev_kid_[nev_] = (char)gemm_kernel_id(g, f32);
+  main();
+  ev_kid_[nev_] = (char)kid;
   check(hipEventRecord(ev_[2 * nev_ + 1], s), "event record");
   launch_gemm_reduce(g, s);
   ev_flops_[nev_] = 2.0 * g.M * g.N * g.K * g.batch;
@@ -1295,7 +1711,7 @@ void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32) {
 }
 
 void Executor::shape_report(FILE* f, int top) const {
-  static const char* names[4] = {"f64", "f64/two", "f32", "f32/two"};
+  static const char* names[NGEMMK] = {"f64", "f64/two", "f32", "f32/two", "f64/sum", "f32/sum"};
   std::vector<std::pair<std::array<int64_t, 6>, ShapeStat>> v(shapes_.begin(), shapes_.end());
   std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
   std::fprintf(f, "gemm shapes by time (M N K batch splits kernel: launches, ms, TFLOP/s)\n");
@@ -1306,7 +1722,7 @@ void Executor::shape_report(FILE* f, int top) const {
                  (long long)k[2], (long long)k[3], (long long)k[4], names[k[5]], (long long)st.n, st.ms,
                  st.ms > 0 ? st.flops / (st.ms * 1e9) : 0.0);
   }
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < NGEMMK; ++q)
     if (kernel_launches[q])
       std::fprintf(f, "  kernel %-7s: %lld launches, %.1f ms, %.2f TFLOP/s\n", names[q], (long long)kernel_launches[q],
                    kernel_ms[q], kernel_flops[q] / (kernel_ms[q] * 1e9));
@@ -1316,6 +1732,7 @@ double Executor::flops(const std::vector<int>& list) const {
   double f = 0;
   for (int k : list)
     if (g_.ops[k].kind == OpKind::Contract) {
+      // (multi-segment plans hold the total summed extent in g.K)
       const ContractPlan& p = plans_[k];
       if (p.dot)
         f += 2.0 * p.g.K;
@@ -1367,10 +1784,29 @@ void Executor::run(const std::vector<int>& list, hipStream_t s) {
 
 void Executor::run_op(int k, hipStream_t s) {
   const Op& op = g_.ops[k];
+  if (op.kind == OpKind::Nop) return;
   if (g_.t[op.out].offset < 0) throw std::runtime_error("op without storage (not in any program)");
   switch (op.kind) {
+    case OpKind::Nop:
+      break;
     case OpKind::Contract: {
       const ContractPlan& p = plans_[k];
+      if (p.kind == ContractKind::Multi) {
+        for (const PermArgs& pk : p.spacks) launch_perm(pk, s);
+        GemmMulti gm{};
+        gm.g = p.g;
+        gm.nseg = (int)p.segs.size();
+        for (int q = 0; q < gm.nseg; ++q) gm.seg[q] = p.segs[q];
+        const bool f32 = lowp_ && p.g.M >= 64 && p.g.N >= 64 && p.g.K >= 64;
+        if (prof_) {
+          timed_gemm(p.g, s, f32, &gm);
+        } else {
+          launch_gemm_multi(gm, s, f32);
+          launch_gemm_reduce(p.g, s);
+        }
+        if (p.tmpC) launch_perm(p.pc, s);
+        break;
+      }
       if (p.packA) launch_perm(p.pa, s);
       if (p.packB) launch_perm(p.pb, s);
       if (p.dot) {

@@ -65,9 +65,32 @@ struct PermArgs {
 void launch_gemm(const GemmArgs& a, hipStream_t s);
 // the MFMA kernel alone, and the split-K reduction that follows it
 void launch_gemm_main(const GemmArgs& a, hipStream_t s, bool f32 = false);
+// One product of a multi-segment GEMM: C += alpha * A_s B_s over the
+// segment's own summed extent K (positions k0 .. k0 + K - 1 of the
+// concatenated summed index).  Every group may span two runs (IdxMap, single
+// runs given as D = 2^31).
+struct GemmSeg {
+  const double* A;
+  const double* B;
+  int64_t K, k0;
+  int64_t sAm, sAk, sBk, sBn, sAb, sBb;
+  IdxMap mAm, mAk, mBk, mBn;
+  double alpha;
+};
+constexpr int MAXSEG = 16;
+// C = sum over segments (+ beta Cin): g holds the output, the total summed
+// extent and the split-K plan (g.A, g.B unused, g.alpha = 1)
+struct GemmMulti {
+  GemmArgs g;
+  int nseg;
+  GemmSeg seg[MAXSEG];
+};
+void launch_gemm_multi(const GemmMulti& m, hipStream_t s, bool f32 = false);
+
 // the GEMM kernels: FP64 or FP32 products, operand groups of one run each or
-// of up to two runs
-enum GemmKernel { GEMM_F64 = 0, GEMM_F64_TWO = 1, GEMM_F32 = 2, GEMM_F32_TWO = 3 };
+// of up to two runs, several products summed in one pass
+enum GemmKernel { GEMM_F64 = 0, GEMM_F64_TWO = 1, GEMM_F32 = 2, GEMM_F32_TWO = 3, GEMM_F64_MULTI = 4,
+                  GEMM_F32_MULTI = 5, NGEMMK = 6 };
 inline int gemm_kernel_id(const GemmArgs& a, bool f32) { return (f32 ? 2 : 0) + (a.two ? 1 : 0); }
 void launch_gemm_reduce(const GemmArgs& a, hipStream_t s);
 // y[i] += sum_j coef[j] X[j][i] over X [k][n] (coef: device, k entries)
@@ -110,7 +133,7 @@ struct GemvArgs {
 void launch_gemv(const GemvArgs& g, hipStream_t s);
 // K == 1: C[b][m][n] = alpha A[b][m] B[b][n] + beta Cin[b][m][n]
 
-enum class ContractKind { Mfma, Dot, Gemv, Outer };
+enum class ContractKind { Mfma, Dot, Gemv, Outer, Multi };
 
 struct ContractPlan {
   // operand packs: -1 = use directly
@@ -120,6 +143,9 @@ struct ContractPlan {
   GemmArgs g{};
   PermArgs pa{}, pb{}, pc{};
   int64_t scratch = 0;  // doubles of scratch needed
+  // Multi: the products (g holds the output side) and their operand packs
+  std::vector<GemmSeg> segs;
+  std::vector<PermArgs> spacks;
 };
 
 class Executor {
@@ -138,8 +164,8 @@ class Executor {
   void flush_profile();
   // timed totals per GEMM kernel (GemmKernel): milliseconds, algorithmic
   // flops (2 M N K per launch), launches
-  double kernel_ms[4] = {}, kernel_flops[4] = {};
-  int64_t kernel_launches[4] = {};
+  double kernel_ms[NGEMMK] = {}, kernel_flops[NGEMMK] = {};
+  int64_t kernel_launches[NGEMMK] = {};
   // reduced precision: dense contractions (M, N, K >= 64) take FP32 products
   void set_lowp(bool on) { lowp_ = on; }
   bool lowp() const { return lowp_; }
@@ -182,7 +208,7 @@ class Executor {
   std::map<std::array<int64_t, 6>, ShapeStat> shapes_;
   size_t nev_ = 0;
   void run_op(int k, hipStream_t s);
-  void timed_gemm(const GemmArgs& g, hipStream_t s, bool f32);
+  void timed_gemm(const GemmArgs& g, hipStream_t s, bool f32, const GemmMulti* multi = nullptr);
 };
 
 ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* scratch);

@@ -184,6 +184,8 @@ std::vector<int> Graph::jvp(int begin, int end, const std::map<int, int>& seeds)
     const Op op = ops[k];  // copy: ops may reallocate
     int res = -1;
     switch (op.kind) {
+      case OpKind::Nop:
+        break;
       case OpKind::Contract: {
         std::string spec = op.la + "," + op.lb + "->" + op.lo;
         int cur = -1;
@@ -263,6 +265,8 @@ std::map<int, int> Graph::vjp(int begin, int end, const std::map<int, int>& seed
     const Op op = ops[k];
     if (!dep[op.out]) continue;
     switch (op.kind) {
+      case OpKind::Nop:
+        break;
       case OpKind::Contract: {
         Term g;
         if (!term(op.out, g)) break;
@@ -331,6 +335,8 @@ std::vector<int> Graph::batchify(const std::vector<int>& list, const std::vector
     const Op op = ops[k];  // copy: ops may reallocate
     int res = -1;
     switch (op.kind) {
+      case OpKind::Nop:
+        break;
       case OpKind::Contract: {
         int a = B(op.a), b = B(op.b), c0 = op.c0 >= 0 ? B(op.c0) : -1;
         if (a < 0 && b < 0) continue;
@@ -427,6 +433,12 @@ static std::vector<int> op_inputs(const Op& op) {
     case OpKind::Contract:
       r = {op.a, op.b};
       if (op.c0 >= 0) r.push_back(op.c0);
+      for (const Seg& sg : op.segs) {
+        r.push_back(sg.a);
+        r.push_back(sg.b);
+      }
+      break;
+    case OpKind::Nop:
       break;
     case OpKind::Lincomb:
       r = op.ins;
@@ -439,8 +451,158 @@ static std::vector<int> op_inputs(const Op& op) {
   return r;
 }
 
+int Graph::fuse_sums(const std::vector<const std::vector<int>*>& programs, const std::vector<int>& pinned) {
+  constexpr size_t MAXSEG = 16;  // products per fused op (longer sums chain through the addend)
+  const int64_t lim32 = (int64_t)1 << 31;
+  const int nt = (int)t.size();
+  std::vector<std::vector<int>> op_progs(ops.size());
+  for (int p = 0; p < (int)programs.size(); ++p)
+    for (int k : *programs[p])
+      if (op_progs[k].empty() || op_progs[k].back() != p) op_progs[k].push_back(p);
+  std::vector<int> nread(nt, 0), producer(nt, -1);
+  std::vector<char> pin(nt, 0);
+  for (int i : pinned)
+    if (i >= 0 && i < nt) pin[i] = 1;
+  for (size_t k = 0; k < ops.size(); ++k) {
+    if (op_progs[k].empty()) continue;
+    for (int in : op_inputs(ops[k])) ++nread[in];
+    if (ops[k].out >= 0) producer[ops[k].out] = (int)k;
+  }
+  int absorbed = 0;
+  for (size_t kl = 0; kl < ops.size(); ++kl) {
+    if (ops[kl].kind != OpKind::Lincomb || op_progs[kl].empty()) continue;
+    const Op L = ops[kl];
+    // candidate terms grouped by how their output indices split between
+    // batch, first-operand and second-operand indices (in L's names)
+    std::map<std::string, std::vector<size_t>> groups;
+    for (size_t i = 0; i < L.ins.size(); ++i) {
+      const int ti = L.ins[i];
+      const int kp = producer[ti];
+      if (kp < 0 || kp >= (int)kl) continue;
+      const Op& P = ops[kp];
+      if (P.kind != OpKind::Contract || P.c0 >= 0 || !P.segs.empty()) continue;
+      if (pin[ti] || nread[ti] != 1 || op_progs[kp] != op_progs[kl]) continue;
+      if (t[P.a].size() >= lim32 || t[P.b].size() >= lim32 || t[ti].size() >= lim32) continue;
+      std::string M, N, B;
+      for (size_t q = 0; q < P.lo.size(); ++q) {
+        const char c = P.lo[q], o = L.lin[i][q];
+        const bool ia = P.la.find(c) != std::string::npos, ib = P.lb.find(c) != std::string::npos;
+        (ia && ib ? B : ia ? M : N) += o;
+      }
+      // rows or columns fewer than a matrix-core tile: memory-bound shapes
+      // that stay with their own kernels
+      int64_t ms = 1, ns = 1;
+      for (char c : M) ms *= t[L.out].dim[L.lo.find(c)];
+      for (char c : N) ns *= t[L.out].dim[L.lo.find(c)];
+      if (ms < 16 || ns < 16) continue;
+      std::sort(M.begin(), M.end());
+      std::sort(N.begin(), N.end());
+      std::sort(B.begin(), B.end());
+      groups[B + "|" + std::min(M, N) + "|" + std::max(M, N)].push_back(i);
+    }
+    std::vector<char> taken(L.ins.size(), 0);
+    std::vector<Term> fused_terms;
+    int nfused_groups = 0;
+    for (auto& kv : groups) {
+      std::vector<size_t> idx = kv.second;
+      if (idx.size() < 2) continue;
+      std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return producer[L.ins[x]] < producer[L.ins[y]]; });
+      ++nfused_groups;
+      // the first member's first-operand output indices set the orientation
+      std::string mref;
+      bool have_ref = false;
+      int prev = -1;
+      for (size_t c0 = 0; c0 < idx.size(); c0 += MAXSEG) {
+        const size_t c1 = std::min(idx.size(), c0 + MAXSEG);
+        std::vector<Seg> segs;
+        for (size_t j = c0; j < c1; ++j) {
+          const size_t i = idx[j];
+          const Op& P = ops[producer[L.ins[i]]];
+          // P's index names -> L's; summed indices get names unused by L
+          std::map<char, char> ren;
+          for (size_t q = 0; q < P.lo.size(); ++q) ren[P.lo[q]] = L.lin[i][q];
+          std::string used = L.lo;
+          char next = 'A';
+          for (const std::string* l : {&P.la, &P.lb})
+            for (char c : *l)
+              if (!ren.count(c)) {
+                while (used.find(next) != std::string::npos) ++next;
+                ren[c] = next;
+                used += next;
+              }
+          Seg sg{P.a, P.b, "", "", P.alpha * L.coef[i]};
+          for (char c : P.la) sg.la += ren[c];
+          for (char c : P.lb) sg.lb += ren[c];
+          std::string am;
+          for (char c : L.lo)
+            if (sg.la.find(c) != std::string::npos && sg.lb.find(c) == std::string::npos) am += c;
+          if (!have_ref) {
+            mref = am;
+            have_ref = true;
+          }
+          if (am != mref) {
+            std::swap(sg.a, sg.b);
+            std::swap(sg.la, sg.lb);
+          }
+          segs.push_back(sg);
+        }
+        const bool last = c1 == idx.size();
+        const bool whole = last && idx.size() == L.ins.size();
+        const int out = whole ? L.out : tensor(dims(L.out), "s");
+        const int kf = producer[L.ins[idx[c1 - 1]]];
+        for (size_t j = c0; j < c1; ++j) {
+          const int kp = producer[L.ins[idx[j]]];
+          t[L.ins[idx[j]]].unused = true;
+          ops[kp] = Op{};
+          ops[kp].kind = OpKind::Nop;
+        }
+        Op f;
+        f.kind = OpKind::Contract;
+        f.out = out;
+        f.a = segs[0].a;
+        f.b = segs[0].b;
+        f.la = segs[0].la;
+        f.lb = segs[0].lb;
+        f.lo = L.lo;
+        f.alpha = segs[0].alpha;
+        f.c0 = prev;
+        f.beta = 1.0;
+        f.segs.assign(segs.begin() + 1, segs.end());
+        ops[kf] = f;
+        absorbed += (int)(c1 - c0);
+        prev = out;
+      }
+      for (size_t i : idx) taken[i] = 1;
+      fused_terms.push_back({1.0, prev, L.lo});
+    }
+    if (!nfused_groups) continue;
+    if (nfused_groups == 1 && fused_terms[0].id == L.out) {
+      ops[kl] = Op{};
+      ops[kl].kind = OpKind::Nop;
+      continue;
+    }
+    Op& Lm = ops[kl];
+    Lm.ins.clear();
+    Lm.coef.clear();
+    Lm.lin.clear();
+    for (size_t i = 0; i < L.ins.size(); ++i)
+      if (!taken[i]) {
+        Lm.ins.push_back(L.ins[i]);
+        Lm.coef.push_back(L.coef[i]);
+        Lm.lin.push_back(L.lin[i]);
+      }
+    for (const Term& tm : fused_terms) {
+      Lm.ins.push_back(tm.id);
+      Lm.coef.push_back(tm.coef);
+      Lm.lin.push_back(tm.labels);
+    }
+  }
+  return absorbed;
+}
+
 int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, const std::vector<int>& pinned,
                         int64_t align) {
+  fuse_sums(programs, pinned);
   auto rnd = [&](int64_t n) { return (n + align - 1) / align * align; };
   const int nt = (int)t.size();
   // owner program of each tensor's producer and of each consumer (-2: several)
@@ -448,6 +610,7 @@ int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, co
   for (int p = 0; p < (int)programs.size(); ++p)
     for (int k : *programs[p]) op_prog[k] = op_prog[k] == -1 || op_prog[k] == p ? p : -2;
   for (size_t k = 0; k < ops.size(); ++k) {
+    if (ops[k].kind == OpKind::Nop) continue;
     const int p = op_prog[k];
     int& pp = prod_prog[ops[k].out];
     pp = pp == -1 ? (p >= 0 ? p : -2) : -2;
@@ -462,8 +625,10 @@ int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, co
   std::vector<char> temp(nt, 0), dead(nt, 0);
   for (size_t k = 0; k < ops.size(); ++k) {
     // produced by an op no program runs: never computed, needs no storage
-    if (op_prog[k] == -1) dead[ops[k].out] = 1;
+    if (op_prog[k] == -1 && ops[k].out >= 0) dead[ops[k].out] = 1;
   }
+  for (int i = 0; i < nt; ++i)
+    if (t[i].unused) dead[i] = 1;
   for (size_t k = 0; k < ops.size(); ++k)
     if (op_prog[k] != -1)
       for (int in : op_inputs(ops[k]))
@@ -502,7 +667,7 @@ int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, co
         }
       }
       const int out = ops[list[j]].out;
-      if (!temp[out] || prod_prog[out] != p) continue;
+      if (out < 0 || !temp[out] || prod_prog[out] != p) continue;
       const int64_t need = rnd(t[out].size());
       int64_t at = 0;
       for (auto& b : used) {

@@ -25,6 +25,7 @@ struct TensorDesc {
   int nd = 0;
   std::array<int64_t, MAXD> dim{};
   bool zero = false;        // identically zero: no storage, never read
+  bool unused = false;      // no longer computed or read (fused away)
   int64_t offset = -1;      // arena offset in doubles (assigned by finalize)
   std::string name;
   int64_t size() const {
@@ -34,15 +35,24 @@ struct TensorDesc {
   }
 };
 
-enum class OpKind { Contract, Lincomb, Slice, Embed };
+enum class OpKind { Contract, Lincomb, Slice, Embed, Nop };
+
+// One more product summed into a contraction's output (same output indices)
+struct Seg {
+  int a, b;
+  std::string la, lb;
+  double alpha;
+};
 
 struct Op {
   OpKind kind;
   int out = -1;
   // Contract: out = alpha * sum A[la] B[lb] -> [lo]  (+ beta * c0)
+  //               + sum over segs of s.alpha * sum A_s[s.la] B_s[s.lb]
   int a = -1, b = -1, c0 = -1;
   double alpha = 1.0, beta = 1.0;
   std::string la, lb, lo;
+  std::vector<Seg> segs;
   // Lincomb: out[lo] = sum_i coef_i * ins_i[lin_i]
   std::vector<int> ins;
   std::vector<double> coef;
@@ -113,8 +123,17 @@ class Graph {
   // other tensors get storage of their own.
   // Tensors in `pinned` (read or written by host code) always get storage of
   // their own.
+  // First fuses sums of products (fuse_sums), then assigns storage.
   int64_t finalize(const std::vector<const std::vector<int>*>& programs, const std::vector<int>& pinned,
                    int64_t align = 32);
+
+  // Sums of products: where a lincomb adds the outputs of contractions that
+  // nothing else reads and whose output indices split the same way between
+  // their two operands, those contractions become the segments of one
+  // contraction (the products accumulate in one pass over the output, no
+  // intermediate tensors).  The absorbed ops become Nop, their outputs
+  // unused.  Returns the number of contractions absorbed.
+  int fuse_sums(const std::vector<const std::vector<int>*>& programs, const std::vector<int>& pinned);
 
  private:
   void check_labels(const std::string& l, int id, const char* what) const;

@@ -2073,7 +2073,7 @@ int scc_get(scc_ctx* c, int field, int k, double* out) {
 }
 
 int scc_profile(scc_ctx* c, int enable, int kernel, double* gemm_ms, double* gemm_flops, long long* gemm_launches) {
-  if (!c || kernel < 0 || kernel > 3) return SCC_EINVAL;
+  if (!c || kernel < 0 || kernel >= NGEMMK) return SCC_EINVAL;
   return guarded(c, nullptr, [&]() -> int {
     const bool was_on = c->ex->profiling();
     c->ex->flush_profile();
