@@ -288,131 +288,104 @@ __device__ __forceinline__ void gemm_multi_body(const GemmMulti& G,
   v4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
-  // The slabs of all segments form one sequence; the loads of the next slab
-  // (possibly the first of the next segment) are in flight while the matrix
-  // cores work on the current one.
-  struct Cur {
-    const double* A;
-    const double* B;
-    int64_t le;
-    bool a_kfast, b_nfast;
-    double alpha;
-  } cur{};
-  int cs = 0;  // segment of the slab being loaded
-  uint32_t aoff[EA], boff[EB];
-  double ra[EA], rb[EB];
-  auto a_pos = [&](bool kfast, int e, int& mm, int& kk) {
-    const int idx = tid + e * GEMM_THREADS;
-    if (kfast) {
-      kk = idx % BKT;
-      mm = idx / BKT;
-    } else {
-      mm = idx % BM;
-      kk = idx / BM;
+  for (int sg = 0; sg < G.nseg; ++sg) {
+    const GemmSeg& S = G.seg[sg];
+    const int64_t lb = max(kbeg - S.k0, (int64_t)0), le = min(kend - S.k0, S.K);
+    if (lb >= le) continue;  // the same for the whole block
+    const double* A = S.A + bz * S.sAb;
+    const double* B = S.B + bz * S.sBb;
+    const bool a_kfast = (S.sAk == 1);
+    const bool b_nfast = (S.sBn == 1) || (S.sBk != 1);
+    auto a_pos = [&](int e, int& mm, int& kk) {
+      const int idx = tid + e * GEMM_THREADS;
+      if (a_kfast) {
+        kk = idx % BKT;
+        mm = idx / BKT;
+      } else {
+        mm = idx % BM;
+        kk = idx / BM;
+      }
+    };
+    auto b_pos = [&](int e, int& nn, int& kk) {
+      const int idx = tid + e * GEMM_THREADS;
+      if (b_nfast) {
+        nn = idx % BN;
+        kk = idx / BN;
+      } else {
+        kk = idx % BKT;
+        nn = idx / BKT;
+      }
+    };
+    uint32_t aoff[EA], boff[EB];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      int mm, kk;
+      a_pos(e, mm, kk);
+      const int64_t gm = m0 + mm;
+      aoff[e] = gm < a.M ? imap32((uint32_t)gm, S.mAm, S.sAm) : 0u;
     }
-  };
-  auto b_pos = [&](bool nfast, int e, int& nn, int& kk) {
-    const int idx = tid + e * GEMM_THREADS;
-    if (nfast) {
-      nn = idx % BN;
-      kk = idx / BN;
-    } else {
-      kk = idx % BKT;
-      nn = idx / BKT;
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      int nn, kk;
+      b_pos(e, nn, kk);
+      const int64_t gn = n0 + nn;
+      boff[e] = gn < a.N ? imap32((uint32_t)gn, S.mBn, S.sBn) : 0u;
     }
-  };
-  // first segment at or after sg with summed indices in this block's range
-  auto open_seg = [&](int sg, int64_t& lb) -> int {
-    for (; sg < G.nseg; ++sg) {
-      const GemmSeg& S = G.seg[sg];
-      lb = max(kbeg - S.k0, (int64_t)0);
-      const int64_t le = min(kend - S.k0, S.K);
-      if (lb >= le) continue;
-      cs = sg;
-      cur.A = S.A + bz * S.sAb;
-      cur.B = S.B + bz * S.sBb;
-      cur.le = le;
-      cur.a_kfast = (S.sAk == 1);
-      cur.b_nfast = (S.sBn == 1) || (S.sBk != 1);
-      cur.alpha = S.alpha;
+    double ra[EA], rb[EB];
+    auto load = [&](int64_t k0) {
 #pragma unroll
       for (int e = 0; e < EA; ++e) {
         int mm, kk;
-        a_pos(cur.a_kfast, e, mm, kk);
-        const int64_t gm = m0 + mm;
-        aoff[e] = gm < a.M ? imap32((uint32_t)gm, S.mAm, S.sAm) : 0u;
+        a_pos(e, mm, kk);
+        const int64_t gm = m0 + mm, gk = k0 + kk;
+        ra[e] = (gm < a.M && gk < le) ? A[aoff[e] + imap32((uint32_t)gk, S.mAk, S.sAk)] : 0.0;
       }
 #pragma unroll
       for (int e = 0; e < EB; ++e) {
         int nn, kk;
-        b_pos(cur.b_nfast, e, nn, kk);
-        const int64_t gn = n0 + nn;
-        boff[e] = gn < a.N ? imap32((uint32_t)gn, S.mBn, S.sBn) : 0u;
+        b_pos(e, nn, kk);
+        const int64_t gn = n0 + nn, gk = k0 + kk;
+        rb[e] = (gn < a.N && gk < le) ? B[boff[e] + imap32((uint32_t)gk, S.mBk, S.sBk)] : 0.0;
       }
-      return sg;
-    }
-    return -1;
-  };
-  auto load = [&](int64_t k0) {
-    const GemmSeg& S = G.seg[cs];
+    };
+    const double alpha = S.alpha;
+    load(lb);
+    for (int64_t k0 = lb; k0 < le; k0 += BKT) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      int mm, kk;
-      a_pos(cur.a_kfast, e, mm, kk);
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      ra[e] = (gm < a.M && gk < cur.le) ? cur.A[aoff[e] + imap32((uint32_t)gk, S.mAk, S.sAk)] : 0.0;
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      int nn, kk;
-      b_pos(cur.b_nfast, e, nn, kk);
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      rb[e] = (gn < a.N && gk < cur.le) ? cur.B[boff[e] + imap32((uint32_t)gk, S.mBk, S.sBk)] : 0.0;
-    }
-  };
-  int64_t k0 = 0;
-  int sg = open_seg(0, k0);
-  if (sg >= 0) load(k0);
-  while (sg >= 0) {
-    // the registers hold slab k0 of segment sg
-    const bool kf = cur.a_kfast, nf = cur.b_nfast;
-    const double alpha = cur.alpha;
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      int mm, kk;
-      a_pos(kf, e, mm, kk);
-      As[kk][mm] = (T)(alpha * ra[e]);
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      int nn, kk;
-      b_pos(nf, e, nn, kk);
-      Bs[kk][nn] = (T)rb[e];
-    }
-    __syncthreads();
-    k0 += BKT;
-    if (k0 >= cur.le) sg = open_seg(sg + 1, k0);
-    if (sg >= 0) load(k0);
-#pragma unroll
-    for (int kk = 0; kk < BKT; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      T af[2], bf[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        af[t] = As[kr][wm + t * 16 + (lane & 15)];
-        bf[t] = Bs[kr][wn + t * 16 + (lane & 15)];
+      for (int e = 0; e < EA; ++e) {
+        int mm, kk;
+        a_pos(e, mm, kk);
+        As[kk][mm] = (T)(alpha * ra[e]);
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int e = 0; e < EB; ++e) {
+        int nn, kk;
+        b_pos(e, nn, kk);
+        Bs[kk][nn] = (T)rb[e];
+      }
+      __syncthreads();
+      if (k0 + BKT < le) load(k0 + BKT);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if constexpr (F32)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
-          else
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      for (int kk = 0; kk < BKT; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        T af[2], bf[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          af[t] = As[kr][wm + t * 16 + (lane & 15)];
+          bf[t] = Bs[kr][wn + t * 16 + (lane & 15)];
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            if constexpr (F32)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   const bool part = a.splits > 1;
   double* out = part ? a.P + split * a.M * a.N : a.C + bz * a.sCb;
