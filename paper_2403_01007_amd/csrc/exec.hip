@@ -619,8 +619,15 @@ void launch_gemm(const GemmArgs& a, hipStream_t s) {
   launch_gemm_reduce(a, s);
 }
 
-__global__ void combine_kernel(const double* __restrict__ X, int k, int64_t n, const double* __restrict__ coef,
+// coefficients travel as kernel arguments (no host-to-device copy)
+constexpr int COMBINE_MAXC = 224;
+struct CombineCoef {
+  double c[COMBINE_MAXC];
+};
+
+__global__ void combine_kernel(const double* __restrict__ X, int k, int64_t n, CombineCoef cf,
                                double* __restrict__ y) {
+  const double* coef = cf.c;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double acc = y[i];
@@ -730,8 +737,14 @@ void launch_gemv(const GemvArgs& g, hipStream_t s) {
 
 void launch_combine(const double* X, int k, int64_t n, const double* coef, double* y, hipStream_t s) {
   if (k <= 0 || n <= 0) return;
-  hipLaunchKernelGGL(combine_kernel, dim3(grid_for(n)), dim3(256), 0, s, X, k, n, coef, y);
-  check(hipGetLastError(), "combine launch");
+  // chunks of vectors in order: the additions keep the serial order
+  for (int j0 = 0; j0 < k; j0 += COMBINE_MAXC) {
+    const int kc = std::min(COMBINE_MAXC, k - j0);
+    CombineCoef cf;
+    for (int j = 0; j < kc; ++j) cf.c[j] = coef[j0 + j];
+    hipLaunchKernelGGL(combine_kernel, dim3(grid_for(n)), dim3(256), 0, s, X + (int64_t)j0 * n, kc, n, cf, y);
+    check(hipGetLastError(), "combine launch");
+  }
 }
 
 // Index arithmetic of the permutation kernel in 32 bits: n / d for

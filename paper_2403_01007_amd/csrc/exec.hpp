@@ -93,7 +93,8 @@ enum GemmKernel { GEMM_F64 = 0, GEMM_F64_TWO = 1, GEMM_F32 = 2, GEMM_F32_TWO = 3
                   GEMM_F32_MULTI = 5, NGEMMK = 6 };
 inline int gemm_kernel_id(const GemmArgs& a, bool f32) { return (f32 ? 2 : 0) + (a.two ? 1 : 0); }
 void launch_gemm_reduce(const GemmArgs& a, hipStream_t s);
-// y[i] += sum_j coef[j] X[j][i] over X [k][n] (coef: device, k entries)
+// y[i] += sum_j coef[j] X[j][i] over X [k][n] (coef: host, k entries, read
+// before the call returns)
 void launch_combine(const double* X, int k, int64_t n, const double* coef, double* y, hipStream_t s);
 void launch_perm(const PermArgs& a, hipStream_t s);
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);

@@ -314,8 +314,8 @@ std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, co
 void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* devcoef,
                 double* y) {
   if (k == 0) return;
-  c->xfer(devcoef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice);
-  launch_combine(Xb, k, n, devcoef, y, c->s);
+  (void)devcoef;
+  launch_combine(Xb, k, n, coef.data(), y, c->s);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,12 +461,21 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     for (int i = 0; i < nv; ++i)
       for (int j = 0; j < nv; ++j) Gs[i * nv + j] = G[i * maxsub + j];
     std::vector<cplx> w, Y;
-    if (!eig_nonsym(nv, Gs, w, Y)) throw SccError(SCC_ENOCONV, "subspace eigensolver failed");
+    if (!eig_nonsym(nv, Gs, w, Y, false)) throw SccError(SCC_ENOCONV, "subspace eigensolver failed");
     std::vector<int> ord(nv);
     for (int i = 0; i < nv; ++i) ord[i] = i;
     std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
     const int nr_now = std::min(nw_, nv);
     const int nx = std::min(nkeep, nv);
+    // eigenvectors of the Ritz values kept only
+    Y.assign(nv * nv, 0.0);
+    {
+      std::vector<cplx> y;
+      for (int k = 0; k < nx; ++k) {
+        eig_nonsym_vector(nv, Gs, w[ord[k]], y);
+        for (int j = 0; j < nv; ++j) Y[j * nv + ord[k]] = y[j];
+      }
+    }
     double maxres = 0;
     std::vector<double> th(nx);
     std::vector<char> conv(nx, 0);

@@ -64,7 +64,63 @@ inline bool solve_complex(int n, std::vector<cplx> A, std::vector<cplx>& b) {
 
 // Eigenvalues w[n] and right eigenvectors V (column k = V[i*n+k]) of a real
 // nonsymmetric matrix A (row-major).  Returns false if QR fails to converge.
-inline bool eig_nonsym(int n, const std::vector<double>& A, std::vector<cplx>& w, std::vector<cplx>& V) {
+// One eigenvector of A (n x n, row-major) for the eigenvalue lam, by inverse
+// iteration: one LU factorisation of A - lam' (lam nudged off the exact
+// eigenvalue), three solves; normalised, largest component real positive.
+inline void eig_nonsym_vector(int n, const std::vector<double>& A, cplx lam, std::vector<cplx>& x) {
+  double anorm = 0;
+  for (int i = 0; i < n * n; ++i) anorm = std::max(anorm, std::fabs(A[i]));
+  lam += cplx(1e-13 * (anorm + 1.0), 0.0);
+  std::vector<cplx> M(n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) M[i * n + j] = A[i * n + j] - (i == j ? lam : cplx(0.0));
+  std::vector<int> piv(n);
+  bool ok = true;
+  for (int k = 0; k < n && ok; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::abs(M[i * n + k]) > std::abs(M[p * n + k])) p = i;
+    piv[k] = p;
+    if (std::abs(M[p * n + k]) == 0.0) {
+      ok = false;
+      break;
+    }
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(M[k * n + j], M[p * n + j]);
+    for (int i = k + 1; i < n; ++i) {
+      const cplx f = M[i * n + k] / M[k * n + k];
+      M[i * n + k] = f;
+      for (int j = k + 1; j < n; ++j) M[i * n + j] -= f * M[k * n + j];
+    }
+  }
+  x.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) x[i] = cplx(1.0 + 0.1 * i, 0.0);
+  for (int it = 0; it < 3 && ok; ++it) {
+    for (int k = 0; k < n; ++k) {
+      if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+      for (int i = k + 1; i < n; ++i) x[i] -= M[i * n + k] * x[k];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      cplx sum = x[i];
+      for (int j = i + 1; j < n; ++j) sum -= M[i * n + j] * x[j];
+      x[i] = sum / M[i * n + i];
+    }
+    double nr = 0;
+    for (auto& z : x) nr += std::norm(z);
+    nr = std::sqrt(nr);
+    for (auto& z : x) z /= nr;
+  }
+  int im = 0;
+  for (int i = 1; i < n; ++i)
+    if (std::abs(x[i]) > std::abs(x[im])) im = i;
+  const cplx ph = std::abs(x[im]) > 0 ? std::conj(x[im]) / std::abs(x[im]) : cplx(1.0);
+  for (int i = 0; i < n; ++i) x[i] *= ph;
+}
+
+// Eigenvalues of a real non-symmetric matrix (Hessenberg reduction, shifted
+// complex QR); with vectors, also every eigenvector (columns of V).
+inline bool eig_nonsym(int n, const std::vector<double>& A, std::vector<cplx>& w, std::vector<cplx>& V,
+                       bool vectors = true) {
   std::vector<cplx> H(n * n);
   for (int i = 0; i < n * n; ++i) H[i] = A[i];
   // Householder reduction to upper Hessenberg form
@@ -151,30 +207,12 @@ inline bool eig_nonsym(int n, const std::vector<double>& A, std::vector<cplx>& w
     }
     for (int i = lo; i <= hi; ++i) H[i * n + i] += mu;
   }
-  // eigenvectors of the original matrix by inverse iteration
+  if (!vectors) return true;
   V.assign(n * n, 0.0);
-  double anorm = 0;
-  for (int i = 0; i < n * n; ++i) anorm = std::max(anorm, std::fabs(A[i]));
+  std::vector<cplx> x;
   for (int k = 0; k < n; ++k) {
-    cplx lam = w[k] + cplx(1e-13 * (anorm + 1.0), 0.0);
-    std::vector<cplx> M(n * n);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) M[i * n + j] = A[i * n + j] - (i == j ? lam : cplx(0.0));
-    std::vector<cplx> x(n, 1.0);
-    for (int i = 0; i < n; ++i) x[i] = cplx(1.0 + 0.1 * i, 0.0);
-    for (int it = 0; it < 3; ++it) {
-      if (!solve_complex(n, M, x)) break;
-      double nr = 0;
-      for (auto& z : x) nr += std::norm(z);
-      nr = std::sqrt(nr);
-      for (auto& z : x) z /= nr;
-    }
-    // make the largest component real positive
-    int im = 0;
-    for (int i = 1; i < n; ++i)
-      if (std::abs(x[i]) > std::abs(x[im])) im = i;
-    cplx ph = std::abs(x[im]) > 0 ? std::conj(x[im]) / std::abs(x[im]) : cplx(1.0);
-    for (int i = 0; i < n; ++i) V[i * n + k] = x[i] * ph;
+    eig_nonsym_vector(n, A, w[k], x);
+    for (int i = 0; i < n; ++i) V[i * n + k] = x[i];
   }
   return true;
 }
