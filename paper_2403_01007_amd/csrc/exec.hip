@@ -43,7 +43,7 @@ __device__ __forceinline__ uint32_t imap32(uint32_t x, const IdxMap& m, int64_t 
   return q * m.so + (x - q * m.D) * (uint32_t)si;
 }
 
-constexpr int BKMAX = 32;
+constexpr int GEMM_BK = 16;  // slab depth of the matrix-core kernels
 
 // Operand tiles are loaded from global memory into registers one K-slab
 // ahead: the loads of slab s+1 are in flight while the matrix cores work on
@@ -203,64 +203,42 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& a,
 
 // FP64 matrix-core GEMM (the contraction kernel of every device program):
 // every operand index group (rows, columns, summed index) is one run of
-// dimensions with one stride
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs a) {
-  __shared__ double As[BKMAX][BM + 1];
-  __shared__ double Bs[BKMAX][BN + 1];
-  if (a.K >= 256)
-    gemm_body<32, false, false>(a, As, Bs);
-  else
-    gemm_body<16, false, false>(a, As, Bs);
+// dimensions with one stride.  Slabs of 16 and at most 128 registers per
+// lane give four waves per SIMD (measured faster than 32-deep slabs at two
+// or three waves: the other waves' matrix work covers each wave's loads,
+// LDS staging and barriers).
+__global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_f64_kernel(
+    GemmArgs a) {
+  __shared__ double As[GEMM_BK][BM + 1];
+  __shared__ double Bs[GEMM_BK][BN + 1];
+  gemm_body<GEMM_BK, false, false>(a, As, Bs);
 }
 
 // The same where some group spans two runs (read in place instead of
 // packing the operand, or writing a temporary, in the group's order)
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_two_kernel(GemmArgs a) {
-  __shared__ double As[BKMAX][BM + 1];
-  __shared__ double Bs[BKMAX][BN + 1];
-  if (a.K >= 256)
-    gemm_body<32, false, true>(a, As, Bs);
-  else
-    gemm_body<16, false, true>(a, As, Bs);
+__global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_f64_two_kernel(
+    GemmArgs a) {
+  __shared__ double As[GEMM_BK][BM + 1];
+  __shared__ double Bs[GEMM_BK][BN + 1];
+  gemm_body<GEMM_BK, false, true>(a, As, Bs);
 }
 
 // Reduced-precision variants: FP64 operands are rounded to FP32 as they are
 // staged into LDS, multiplied on the FP32 matrix cores
 // (v_mfma_f32_16x16x4_f32) with FP32 accumulation, and the result is written
 // back in FP64.  Same tiling and operand mapping as the FP64 kernels.
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_kernel(GemmArgs a) {
-  __shared__ float As[BKMAX][BM + 1];
-  __shared__ float Bs[BKMAX][BN + 1];
-  if (a.K >= 256)
-    gemm_body<32, true, false>(a, As, Bs);
-  else
-    gemm_body<16, true, false>(a, As, Bs);
+__global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_f32acc_kernel(
+    GemmArgs a) {
+  __shared__ float As[GEMM_BK][BM + 1];
+  __shared__ float Bs[GEMM_BK][BN + 1];
+  gemm_body<GEMM_BK, true, false>(a, As, Bs);
 }
 
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_two_kernel(GemmArgs a) {
-  __shared__ float As[BKMAX][BM + 1];
-  __shared__ float Bs[BKMAX][BN + 1];
-  if (a.K >= 256)
-    gemm_body<32, true, true>(a, As, Bs);
-  else
-    gemm_body<16, true, true>(a, As, Bs);
-}
-
-// sum_{s < n} p[s * stride] in the order s = 0, 1, ...: the loads are issued
-// in batches of eight ahead of the additions (latency, not bandwidth, bounds
-// a serial chain of loads)
-__device__ __forceinline__ double ordered_sum(const double* p, int64_t n, int64_t stride) {
-  double v = 0.0;
-  int64_t s = 0;
-  for (; s + 8 <= n; s += 8) {
-    double t[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = p[(s + u) * stride];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v += t[u];
-  }
-  for (; s < n; ++s) v += p[s * stride];
-  return v;
+__global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_f32acc_two_kernel(
+    GemmArgs a) {
+  __shared__ float As[GEMM_BK][BM + 1];
+  __shared__ float Bs[GEMM_BK][BN + 1];
+  gemm_body<GEMM_BK, true, true>(a, As, Bs);
 }
 
 // Multi-segment GEMM: the products of every segment accumulate in the same
@@ -409,22 +387,35 @@ __device__ __forceinline__ void gemm_multi_body(const GemmMulti& G,
       }
 }
 
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_multi_kernel(GemmMulti m) {
-  __shared__ double As[BKMAX][BM + 1];
-  __shared__ double Bs[BKMAX][BN + 1];
-  if (m.g.K >= 256 * m.nseg)
-    gemm_multi_body<32, false>(m, As, Bs);
-  else
-    gemm_multi_body<16, false>(m, As, Bs);
+__global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_f64_multi_kernel(
+    GemmMulti m) {
+  __shared__ double As[GEMM_BK][BM + 1];
+  __shared__ double Bs[GEMM_BK][BN + 1];
+  gemm_multi_body<GEMM_BK, false>(m, As, Bs);
 }
 
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f32acc_multi_kernel(GemmMulti m) {
-  __shared__ float As[BKMAX][BM + 1];
-  __shared__ float Bs[BKMAX][BN + 1];
-  if (m.g.K >= 256 * m.nseg)
-    gemm_multi_body<32, true>(m, As, Bs);
-  else
-    gemm_multi_body<16, true>(m, As, Bs);
+__global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_f32acc_multi_kernel(
+    GemmMulti m) {
+  __shared__ float As[GEMM_BK][BM + 1];
+  __shared__ float Bs[GEMM_BK][BN + 1];
+  gemm_multi_body<GEMM_BK, true>(m, As, Bs);
+}
+
+// sum_{s < n} p[s * stride] in the order s = 0, 1, ...: the loads are issued
+// in batches of eight ahead of the additions (latency, not bandwidth, bounds
+// a serial chain of loads)
+__device__ __forceinline__ double ordered_sum(const double* p, int64_t n, int64_t stride) {
+  double v = 0.0;
+  int64_t s = 0;
+  for (; s + 8 <= n; s += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[(s + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; s < n; ++s) v += p[s * stride];
+  return v;
 }
 
 __global__ void splitk_reduce_kernel(GemmArgs a) {
