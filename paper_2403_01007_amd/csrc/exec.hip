@@ -1377,7 +1377,7 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
   const int64_t lim32 = (int64_t)1 << 31;
   const bool two_ok = !(Bx == 1 && (Mx == 1 || Nx == 1)) && dA.size() < lim32 && dB.size() < lim32 &&
                       dO.size() < lim32;
-  constexpr double GEMM_RATE = 30e12, TWO_PENALTY = 1.07, HBM_RATE = 3e12, LAUNCH_S = 4e-6;
+  constexpr double GEMM_RATE = 30e12, TWO_PENALTY = 1.07, TWO_PENALTY_SHORT = 1.3, HBM_RATE = 3e12, LAUNCH_S = 4e-6;
   const double gemm_s = 2.0 * Mx * Nx * Kx * Bx / GEMM_RATE;
   auto move_s = [&](int64_t elems) { return 16.0 * elems / HBM_RATE + LAUNCH_S; };
   bool two = false;
@@ -1402,7 +1402,14 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
           const bool any_two = (okA && (am.inner || ak.inner)) || (okB && (bk_.inner || bn_.inner)) ||
                                (okC && (cm.inner || cn.inner));
           if (two && !any_two) continue;  // the single-run pass has this one
-          double cost = gemm_s * (any_two ? TWO_PENALTY : 1.0);
+          // a unit-stride group in runs shorter than 16 elements breaks the
+          // coalescing of its loads or stores (measured about 25 % slower)
+          bool short_runs = false;
+          const View2* vs[6] = {&am, &ak, &bk_, &bn_, &cm, &cn};
+          const bool oks[6] = {okA, okA, okB, okB, okC, okC};
+          for (int q = 0; q < 6; ++q)
+            if (oks[q] && vs[q]->inner && vs[q]->stride == 1 && vs[q]->inner < 16) short_runs = true;
+          double cost = gemm_s * (any_two ? (short_runs ? TWO_PENALTY_SHORT : TWO_PENALTY) : 1.0);
           if (!okA) cost += move_s(dA.size());
           if (!okB) cost += move_s(dB.size());
           if (!okC) cost += move_s(dO.size());
