@@ -216,13 +216,15 @@ int scc_get(scc_ctx* ctx, int field, int k, double* out);
  *   SCC_GEMM_F32, SCC_GEMM_F32_TWO, SCC_GEMM_F32_MULTI  the FP32-product
  *                     variants (precision 1)
  * On return (host pointers, any may be NULL): accumulated kernel
- * milliseconds, algorithmic flops (2 M N K per launch) and launches since
- * the context was created.  SCC_EINVAL for another kernel value.  With the
+ * milliseconds, algorithmic flops (2 M N K per launch), launches, and
+ * algorithmic bytes (operands read once, the output written once and read
+ * once when accumulated) since the context was created.  SCC_EINVAL for another kernel value.  With the
  * verbose option, enable = 0 on a profiling context also prints the time per
  * GEMM shape on stderr. */
 enum { SCC_GEMM_F64 = 0, SCC_GEMM_F64_TWO = 1, SCC_GEMM_F32 = 2, SCC_GEMM_F32_TWO = 3, SCC_GEMM_F64_MULTI = 4,
        SCC_GEMM_F32_MULTI = 5 };
-int scc_profile(scc_ctx* ctx, int enable, int kernel, double* gemm_ms, double* gemm_flops, long long* gemm_launches);
+int scc_profile(scc_ctx* ctx, int enable, int kernel, double* gemm_ms, double* gemm_flops, long long* gemm_launches,
+                double* gemm_bytes);
 
 /* Test hooks on the device programs (inputs/outputs device pointers):
  *   residual at given amplitudes (and zeta / X3 states when nstates > 1):

@@ -83,7 +83,8 @@ def load_library():
     lib.scc_eval_residual.argtypes = [P, P, P, P, P]
     lib.scc_eval_sigma.argtypes = [P, P, P]
     lib.scc_eval_left.argtypes = [P, P, P]
-    lib.scc_profile.argtypes = [P, I, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]
+    lib.scc_profile.argtypes = [P, I, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
+                                ctypes.POINTER(D)]
     MD = ctypes.POINTER(MlpDims)
     lib.scc_mlp_param_count.argtypes = [MD, ctypes.POINTER(ctypes.c_longlong)]
     lib.scc_mlp_workspace_bytes.argtypes = [MD, I, ctypes.POINTER(S)]
@@ -273,10 +274,11 @@ class Context:
         return out
 
     def profile(self, enable, kernel=GEMM_F64):
-        ms, fl, n = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_longlong(0)
+        """(milliseconds, flops, launches, bytes) of one GEMM kernel so far"""
+        ms, fl, n, by = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_longlong(0), ctypes.c_double(0)
         self._check(self.lib.scc_profile(self.h, 1 if enable else 0, kernel, ctypes.byref(ms), ctypes.byref(fl),
-                                         ctypes.byref(n)), "scc_profile")
-        return ms.value, fl.value, n.value
+                                         ctypes.byref(n), ctypes.byref(by)), "scc_profile")
+        return ms.value, fl.value, n.value, by.value
 
     def eval_left(self, vec):
         out = self.zeros(1 + self.nov + self.nov * self.nov)

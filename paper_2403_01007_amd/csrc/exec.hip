@@ -574,7 +574,8 @@ void launch_gemm_main(const GemmArgs& a, hipStream_t s, bool f32) {
   if (a.splits > 1 && (a.batch != 1 || !a.P || a.kchunk <= 0)) throw std::runtime_error("bad split-K plan");
   dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((a.M + BM - 1) / BM),
             (unsigned)(a.splits > 1 ? a.splits : a.batch));
-  if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm grid too large");
+  if (grid.y > 65535 || grid.z > 65535 || (uint64_t)grid.x * grid.y * grid.z >= ((uint64_t)1 << 32))
+    throw std::runtime_error("gemm grid too large");
   switch (gemm_kernel_id(a, f32)) {
     case GEMM_F64: hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(GEMM_THREADS), 0, s, a); break;
     case GEMM_F64_TWO: hipLaunchKernelGGL(gemm_f64_two_kernel, grid, dim3(GEMM_THREADS), 0, s, a); break;
@@ -597,7 +598,8 @@ void launch_gemm_multi(const GemmMulti& m, hipStream_t s, bool f32) {
   if (a.splits > 1 && (a.batch != 1 || !a.P || a.kchunk <= 0)) throw std::runtime_error("bad split-K plan");
   dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((a.M + BM - 1) / BM),
             (unsigned)(a.splits > 1 ? a.splits : a.batch));
-  if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm grid too large");
+  if (grid.y > 65535 || grid.z > 65535 || (uint64_t)grid.x * grid.y * grid.z >= ((uint64_t)1 << 32))
+    throw std::runtime_error("gemm grid too large");
   if (f32)
     hipLaunchKernelGGL(gemm_f32acc_multi_kernel, grid, dim3(GEMM_THREADS), 0, s, m);
   else
@@ -1625,9 +1627,16 @@ Executor::~Executor() {
   }
 }
 
-void Executor::account(double ms, double flops, const std::array<int64_t, 5>& shape, int kid) {
+// algorithmic bytes of one GEMM launch: both operands read once, the output
+// written once (and read once when accumulated)
+static double gemm_bytes(const GemmArgs& g) {
+  return 8.0 * g.batch * ((double)(g.M + g.N) * g.K + (double)g.M * g.N * (g.Cin ? 2 : 1));
+}
+
+void Executor::account(double ms, double flops, double bytes, const std::array<int64_t, 5>& shape, int kid) {
   kernel_ms[kid] += ms;
   kernel_flops[kid] += flops;
+  kernel_bytes[kid] += bytes;
   ++kernel_launches[kid];
   ShapeStat& st = shapes_[{shape[0], shape[1], shape[2], shape[3], shape[4], kid}];
   st.n += 1;
@@ -1640,6 +1649,7 @@ void Executor::set_profile(bool on) {
     ev_.resize(2 * 4096);
     for (auto& e : ev_) check(hipEventCreate(&e), "event create");
     ev_flops_.resize(4096);
+    ev_bytes_.resize(4096);
     ev_shape_.resize(4096);
     ev_kid_.resize(4096);
   }
@@ -1653,7 +1663,7 @@ void Executor::flush_profile() {
   for (size_t i = 0; i < nev_; ++i) {
     float ms = 0;
     check(hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]), "event elapsed");
-    account(ms, ev_flops_[i], ev_shape_[i], ev_kid_[i]);
+    account(ms, ev_flops_[i], ev_bytes_[i], ev_shape_[i], ev_kid_[i]);
   }
   nev_ = 0;
 }
@@ -1678,6 +1688,7 @@ void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32, const Gemm
     check(hipEventRecord(e1, s), "event record");
     launch_gemm_reduce(g, s);
     cap_->flops.push_back(2.0 * g.M * g.N * g.K * g.batch);
+    cap_->bytes.push_back(gemm_bytes(g));
     cap_->shape.push_back({g.M, g.N, g.K, g.batch, g.splits});
     cap_->kid.push_back((char)kid);
     return;
@@ -1690,6 +1701,7 @@ void Executor::timed_gemm(const GemmArgs& g, hipStream_t s, bool f32, const Gemm
   check(hipEventRecord(ev_[2 * nev_ + 1], s), "event record");
   launch_gemm_reduce(g, s);
   ev_flops_[nev_] = 2.0 * g.M * g.N * g.K * g.batch;
+  ev_bytes_[nev_] = gemm_bytes(g);
   ev_shape_[nev_] = {g.M, g.N, g.K, g.batch, g.splits};
   ++nev_;
 }
@@ -1761,7 +1773,7 @@ void Executor::run(const std::vector<int>& list, hipStream_t s) {
     for (size_t i = 0; i < c.flops.size(); ++i) {
       float ms = 0;
       check(hipEventElapsedTime(&ms, c.ev[2 * i], c.ev[2 * i + 1]), "event elapsed");
-      account(ms, c.flops[i], c.shape[i], c.kid[i]);
+      account(ms, c.flops[i], c.bytes[i], c.shape[i], c.kid[i]);
     }
   }
 }

@@ -164,8 +164,9 @@ class Executor {
   bool profiling() const { return prof_; }
   void flush_profile();
   // timed totals per GEMM kernel (GemmKernel): milliseconds, algorithmic
-  // flops (2 M N K per launch), launches
-  double kernel_ms[NGEMMK] = {}, kernel_flops[NGEMMK] = {};
+  // flops (2 M N K per launch), algorithmic bytes (operands read once, output
+  // written once and read once if accumulated), launches
+  double kernel_ms[NGEMMK] = {}, kernel_flops[NGEMMK] = {}, kernel_bytes[NGEMMK] = {};
   int64_t kernel_launches[NGEMMK] = {};
   // reduced precision: dense contractions (M, N, K >= 64) take FP32 products
   void set_lowp(bool on) { lowp_ = on; }
@@ -191,16 +192,16 @@ class Executor {
     hipGraphExec_t exec = nullptr;
     // profiling variant: event pairs around the GEMM nodes
     std::vector<hipEvent_t> ev;
-    std::vector<double> flops;
+    std::vector<double> flops, bytes;
     std::vector<std::array<int64_t, 5>> shape;
     std::vector<char> kid;
   };
   std::map<std::array<int64_t, 3>, Captured> graphs_cache_;
   Captured* cap_ = nullptr;  // set while a graph is being captured
-  void account(double ms, double flops, const std::array<int64_t, 5>& shape, int kid);
+  void account(double ms, double flops, double bytes, const std::array<int64_t, 5>& shape, int kid);
   std::vector<char> ev_kid_;
   std::vector<hipEvent_t> ev_;
-  std::vector<double> ev_flops_;
+  std::vector<double> ev_flops_, ev_bytes_;
   std::vector<std::array<int64_t, 5>> ev_shape_;
   struct ShapeStat {
     int64_t n = 0;

@@ -2081,7 +2081,8 @@ int scc_get(scc_ctx* c, int field, int k, double* out) {
   });
 }
 
-int scc_profile(scc_ctx* c, int enable, int kernel, double* gemm_ms, double* gemm_flops, long long* gemm_launches) {
+int scc_profile(scc_ctx* c, int enable, int kernel, double* gemm_ms, double* gemm_flops, long long* gemm_launches,
+                double* gemm_bytes) {
   if (!c || kernel < 0 || kernel >= NGEMMK) return SCC_EINVAL;
   return guarded(c, nullptr, [&]() -> int {
     const bool was_on = c->ex->profiling();
@@ -2091,6 +2092,7 @@ int scc_profile(scc_ctx* c, int enable, int kernel, double* gemm_ms, double* gem
     if (gemm_ms) *gemm_ms = c->ex->kernel_ms[kernel];
     if (gemm_flops) *gemm_flops = c->ex->kernel_flops[kernel];
     if (gemm_launches) *gemm_launches = (long long)c->ex->kernel_launches[kernel];
+    if (gemm_bytes) *gemm_bytes = c->ex->kernel_bytes[kernel];
     return SCC_OK;
   });
 }
