@@ -108,6 +108,8 @@ def learned_main(args):
         for k in range(ns):
             Rm[i, k * nst:(k + 1) * nst] = ctx.get(FIELD_R, k)
         Zm[i] = r["zeta"]
+        if (i + 1) % 20 == 0:
+            print(f"[learned: {i + 1} training geometries solved]", file=sys.stderr, flush=True)
     t_data = time.perf_counter() - t0
     print(f"[learned: {args.ntrain} training geometries solved in {t_data:.1f} s]", file=sys.stderr, flush=True)
     kt = min(64, args.ntrain - 1)
@@ -132,6 +134,7 @@ def learned_main(args):
     plain, learned = [], []
     for x in Xte:
         plain.append(solve(x))
+    print(f"[learned: {len(Xte)} held-out geometries solved from the plain start]", file=sys.stderr, flush=True)
     # a fresh context for the learned starts: each held-out geometry inherits
     # only what the previous learned solve left (as along a trajectory)
     ctx.close()
