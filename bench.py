@@ -63,7 +63,7 @@ def learned_main(args):
     import numpy as np
     import torch
     from paper_2403_01007_amd import Context
-    from paper_2403_01007_amd.binding import FIELD_R, FIELD_T, Mlp, pca_expand, pca_fit
+    from paper_2403_01007_amd.binding import FIELD_R, FIELD_T, Mlp, SccError, pca_expand, pca_fit
     from synth_inputs import family_geometries, make_system
 
     S = make_system(args.learned_workload)
@@ -101,18 +101,36 @@ def learned_main(args):
     Tm = torch.empty((args.ntrain, nst - 1), dtype=torch.float64, device=dev)
     Rm = torch.empty((args.ntrain, ns * nst), dtype=torch.float64, device=dev)
     Zm = np.zeros((args.ntrain, npair))
+    def fresh_context():
+        nonlocal ctx
+        ctx.close()
+        ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11)
+
+    # geometries whose solve does not converge from the plain start are left
+    # out (and counted); the context is rebuilt after each such failure
     t0 = time.perf_counter()
+    used, skipped_train = [], 0
     for i, x in enumerate(Xtr):
-        r = solve(x)
-        Tm[i] = ctx.get(FIELD_T)
+        try:
+            r = solve(x)
+        except SccError as e:
+            skipped_train += 1
+            print(f"[learned: training geometry {i} skipped: {e}]", file=sys.stderr, flush=True)
+            fresh_context()
+            continue
+        q = len(used)
+        Tm[q] = ctx.get(FIELD_T)
         for k in range(ns):
-            Rm[i, k * nst:(k + 1) * nst] = ctx.get(FIELD_R, k)
-        Zm[i] = r["zeta"]
+            Rm[q, k * nst:(k + 1) * nst] = ctx.get(FIELD_R, k)
+        Zm[q] = r["zeta"]
+        used.append(i)
         if (i + 1) % 20 == 0:
-            print(f"[learned: {i + 1} training geometries solved]", file=sys.stderr, flush=True)
+            print(f"[learned: {i + 1} training geometries done]", file=sys.stderr, flush=True)
+    ntr = len(used)
+    Xtr, Tm, Rm, Zm = Xtr[used], Tm[:ntr], Rm[:ntr], Zm[:ntr]
     t_data = time.perf_counter() - t0
     print(f"[learned: {args.ntrain} training geometries solved in {t_data:.1f} s]", file=sys.stderr, flush=True)
-    kt = min(64, args.ntrain - 1)
+    kt = min(64, ntr - 1)
     mt, Ut, Ct, _ = pca_fit(Tm, kt)
     mr, Ur, Cr, _ = pca_fit(Rm, kt)
     Y = np.concatenate([Ct.cpu().numpy(), Cr.cpu().numpy(), Zm], axis=1)
@@ -123,33 +141,48 @@ def learned_main(args):
     p0 = np.concatenate([rng.normal(0, 1.0 / np.sqrt(sh[1]), size=sh).ravel() if len(sh) == 2 else np.zeros(sh)
                          for sh in sizes])
     net = Mlp(S.ncoord, nh, nout, p0)
-    batch = min(64, args.ntrain)
-    order = np.stack([rng.permutation(args.ntrain)[:batch] for _ in range(args.train_steps)])
+    batch = min(64, ntr)
+    order = np.stack([rng.permutation(ntr)[:batch] for _ in range(args.train_steps)])
     t1 = time.perf_counter()
     losses = net.train(Xtr, Y, order, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     print(f"[learned: trained {args.train_steps} steps in {t_train:.2f} s, loss {losses[0]:.3e} -> "
           f"{losses[-20:].mean():.3e}]", file=sys.stderr, flush=True)
-    plain, learned = [], []
-    for x in Xte:
-        plain.append(solve(x))
-    print(f"[learned: {len(Xte)} held-out geometries solved from the plain start]", file=sys.stderr, flush=True)
+    plain, learned, held = [], [], []
+    for i, x in enumerate(Xte):
+        try:
+            plain.append(solve(x))
+            held.append(i)
+        except SccError as e:
+            print(f"[learned: held-out geometry {i} skipped (plain start): {e}]", file=sys.stderr, flush=True)
+            fresh_context()
+    print(f"[learned: {len(held)} held-out geometries solved from the plain start]", file=sys.stderr, flush=True)
     # a fresh context for the learned starts: each held-out geometry inherits
     # only what the previous learned solve left (as along a trajectory)
     ctx.close()
     ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11)
-    for x in Xte:
+    failed_learned = 0
+    kept_plain = []
+    for i, x in zip(held, Xte[held]):
         c0 = time.perf_counter()
         yp = net.forward(x[None, :]).to(torch.float64)
         tg = pca_expand(mt, Ut, yp[:, :kt])[0]
         rg = pca_expand(mr, Ur, yp[:, kt:2 * kt])[0]
         guess_r = torch.cat([rg, yp[0, 2 * kt:]])
         t_pred = time.perf_counter() - c0
-        r = solve(x, (tg, guess_r))
+        try:
+            r = solve(x, (tg, guess_r))
+        except SccError as e:
+            failed_learned += 1
+            print(f"[learned: held-out geometry {i} failed from the learned start: {e}]", file=sys.stderr, flush=True)
+            fresh_context()
+            continue
         r["t_exc"] += t_pred
         r["t_all"] += t_pred
         learned.append(r)
+        kept_plain.append(plain[held.index(i)])
+    plain = kept_plain
     dE = max(float(np.abs(a["E"] - b["E"]).max()) for a, b in zip(plain, learned))
     mean = lambda rs, key: float(np.mean([r[key] for r in rs]))
     line = {
@@ -157,8 +190,10 @@ def learned_main(args):
         "value": mean(learned, "t_all"), "unit": "s/geometry", "n_gpus": 1, "steps": args.nheld, "warmup": 0,
         "ms_per_step": 1e3 * mean(learned, "t_all"), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": args.learned_workload, "guess": "learned", "ntrain": args.ntrain,
-                   "nheld": args.nheld, "pca": kt, "mlp": [S.ncoord, nh, nh, nout]},
+        "config": {"workload": args.learned_workload, "guess": "learned", "ntrain": ntr,
+                   "nheld": len(learned), "pca": kt, "mlp": [S.ncoord, nh, nh, nout],
+                   "skipped_training": skipped_train, "skipped_held_out": args.nheld - len(held),
+                   "failed_learned": failed_learned},
         "learned": {"plain_s_per_geometry": mean(plain, "t_all"), "learned_s_per_geometry": mean(learned, "t_all"),
                     "plain_excited_s": mean(plain, "t_exc"), "learned_excited_s": mean(learned, "t_exc"),
                     "plain_iterations": mean(plain, "iters"), "learned_iterations": mean(learned, "iters"),
@@ -184,6 +219,9 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no HIP graphs)")
     ap.add_argument("--no-roofline", action="store_true", help="no per-GEMM event timing in the timed region")
+    ap.add_argument("--all-gemm-events", action="store_true",
+                    help="events around every GEMM kernel's launches in the timed region (default: the "
+                         "multi-product kernel's only)")
     ap.add_argument("--one-target-at-a-time", action="store_true",
                     help="solve the multiplier equations of each gradient / coupling separately")
     ap.add_argument("--learned", action="store_true",
@@ -272,6 +310,11 @@ def main():
         print(f"[warmup step done]", file=sys.stderr, flush=True)
     flops[0] = 0.0
     kernels = range(len(GEMM_KERNEL_NAMES))
+    # events on the multi-product GEMM launches only (the dominant kernel by
+    # the kernel trace), unless every GEMM kernel is asked for
+    if not args.all_gemm_events:
+        ctx.profile_kernels([GEMM_KERNEL_NAMES.index("gemm_f64_multi_kernel"),
+                             GEMM_KERNEL_NAMES.index("gemm_f32acc_multi_kernel")])
     before = [ctx.profile(not args.no_roofline, q) for q in kernels]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -294,6 +337,7 @@ def main():
     # flops of one residual evaluation (for the CPU-baseline scaling)
     nov = S.o * S.v
     t_zero = np.zeros(nov + nov * nov)
+    ctx.profile_kernels(kernels)
     a_fl = sum(ctx.profile(True, q)[1] for q in kernels)
     ctx.eval_residual(t_zero)
     b_fl = sum(ctx.profile(True, q)[1] for q in kernels)

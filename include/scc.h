@@ -226,6 +226,12 @@ enum { SCC_GEMM_F64 = 0, SCC_GEMM_F64_TWO = 1, SCC_GEMM_F32 = 2, SCC_GEMM_F32_TW
 int scc_profile(scc_ctx* ctx, int enable, int kernel, double* gemm_ms, double* gemm_flops, long long* gemm_launches,
                 double* gemm_bytes);
 
+/* Which GEMM kernels scc_profile times: bit k of mask selects kernel k of
+ * the enumeration above (default: all).  Launches of the other kernels run
+ * without events (and add nothing to their totals), which keeps the event
+ * overhead off the timed work when one kernel is of interest. */
+int scc_profile_kernels(scc_ctx* ctx, unsigned mask);
+
 /* Test hooks on the device programs (inputs/outputs device pointers):
  *   residual at given amplitudes (and zeta / X3 states when nstates > 1):
  *     t [t1|t2], zeta [npairs], xs [nstates][1+nov+nov^2] (may be NULL);

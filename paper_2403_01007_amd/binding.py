@@ -19,7 +19,7 @@ GEMM_KERNEL_NAMES = ["gemm_f64_kernel", "gemm_f64_two_kernel", "gemm_f32acc_kern
 EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_last_error",
                     "scc_set_hamiltonian", "scc_set_hamiltonian_fixed_basis", "scc_ground", "scc_excited", "scc_multipliers",
                     "scc_densities", "scc_gradient", "scc_nac", "scc_gradients_and_couplings", "scc_get", "scc_eval_residual",
-                    "scc_eval_sigma", "scc_eval_left", "scc_profile",
+                    "scc_eval_sigma", "scc_eval_left", "scc_profile", "scc_profile_kernels",
                     "scc_mlp_param_count", "scc_mlp_workspace_bytes", "scc_mlp_forward", "scc_mlp_loss_grad",
                     "scc_mlp_train", "scc_pca_workspace_bytes", "scc_pca_fit", "scc_pca_expand"]
 
@@ -85,6 +85,7 @@ def load_library():
     lib.scc_eval_left.argtypes = [P, P, P]
     lib.scc_profile.argtypes = [P, I, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
                                 ctypes.POINTER(D)]
+    lib.scc_profile_kernels.argtypes = [P, ctypes.c_uint]
     MD = ctypes.POINTER(MlpDims)
     lib.scc_mlp_param_count.argtypes = [MD, ctypes.POINTER(ctypes.c_longlong)]
     lib.scc_mlp_workspace_bytes.argtypes = [MD, I, ctypes.POINTER(S)]
@@ -272,6 +273,13 @@ class Context:
         v = self._dev(vec)
         self._check(self.lib.scc_eval_sigma(self.h, _ptr(v), _ptr(out)), "scc_eval_sigma")
         return out
+
+    def profile_kernels(self, kernels):
+        """time only these GEMM kernels (ids) while profiling"""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << k
+        self._check(self.lib.scc_profile_kernels(self.h, mask), "scc_profile_kernels")
 
     def profile(self, enable, kernel=GEMM_F64):
         """(milliseconds, flops, launches, bytes) of one GEMM kernel so far"""

@@ -1794,7 +1794,7 @@ void Executor::run_op(int k, hipStream_t s) {
         gm.nseg = (int)p.segs.size();
         for (int q = 0; q < gm.nseg; ++q) gm.seg[q] = p.segs[q];
         const bool f32 = lowp_ && p.g.M >= 64 && p.g.N >= 64 && p.g.K >= 64;
-        if (prof_) {
+        if (prof_ && (prof_mask_ >> (f32 ? GEMM_F32_MULTI : GEMM_F64_MULTI) & 1u)) {
           timed_gemm(p.g, s, f32, &gm);
         } else {
           launch_gemm_multi(gm, s, f32);
@@ -1814,7 +1814,7 @@ void Executor::run_op(int k, hipStream_t s) {
         if (p.tmpC) launch_perm(p.pc, s);
       } else {
         const bool f32 = lowp_ && p.g.M >= 64 && p.g.N >= 64 && p.g.K >= 64;
-        if (prof_) {
+        if (prof_ && (prof_mask_ >> gemm_kernel_id(p.g, f32) & 1u)) {
           timed_gemm(p.g, s, f32);
         } else {
           launch_gemm_main(p.g, s, f32);

@@ -162,6 +162,8 @@ class Executor {
   // GEMM kernel timing with HIP events (off by default)
   void set_profile(bool on);
   bool profiling() const { return prof_; }
+  // which GEMM kernels get events while profiling (bit k: GemmKernel k)
+  void set_profile_mask(unsigned m) { prof_mask_ = m; }
   void flush_profile();
   // timed totals per GEMM kernel (GemmKernel): milliseconds, algorithmic
   // flops (2 M N K per launch), algorithmic bytes (operands read once, output
@@ -187,6 +189,7 @@ class Executor {
   double* partials_;
   std::vector<ContractPlan> plans_;
   bool prof_ = false, lowp_ = false, graphs_ = false;
+  unsigned prof_mask_ = ~0u;
   struct Captured {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

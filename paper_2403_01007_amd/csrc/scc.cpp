@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "exec.hpp"
+#include "vec.hpp"
 #include "model.hpp"
 #include "smalllinalg.hpp"
 
@@ -356,24 +357,22 @@ void apply_many(scc_ctx* c, bool left, double* const* v, double* const* w, int c
   const StateT& out = left ? m.loutB : m.sigB;
   for (int b0 = 0; b0 < cnt; b0 += nb) {
     const int nc = std::min(nb, cnt - b0);
-    c->fill(c->tp(in.r0), nb, 0.0);
+    std::vector<CopyItem> ci = {{c->tp(in.r0), nullptr, nb}};
     for (int j = 0; j < nb; ++j) {
       double* r1 = c->tp(in.r1) + j * nov;
       double* r2 = c->tp(in.r2) + j * n2;
-      if (j < nc) {
-        c->cp(r1, v[b0 + j], nov);
-        c->cp(r2, v[b0 + j] + nov, n2);
-      } else {
-        c->fill(r1, nov, 0.0);
-        c->fill(r2, n2, 0.0);
-      }
+      ci.push_back({r1, j < nc ? v[b0 + j] : nullptr, nov});
+      ci.push_back({r2, j < nc ? v[b0 + j] + nov : nullptr, n2});
     }
+    launch_copy_list(ci, c->s);
     c->run(left ? m.p_leftB : m.p_sigB);
+    std::vector<CopyItem> co;
     for (int j = 0; j < nc; ++j) {
-      c->cp(w[b0 + j], c->tp(out.r1) + j * nov, nov);
-      c->cp(w[b0 + j] + nov, c->tp(out.r2) + j * n2, n2);
-      c->sym_doubles(w[b0 + j] + nov);
+      co.push_back({w[b0 + j], c->tp(out.r1) + j * nov, nov});
+      co.push_back({w[b0 + j] + nov, c->tp(out.r2) + j * n2, n2});
     }
+    launch_copy_list(co, c->s);
+    for (int j = 0; j < nc; ++j) c->sym_doubles(w[b0 + j] + nov);
   }
 }
 
@@ -1337,30 +1336,34 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
   auto prec = [&](const double* in, double* out) { lag_prec(c, lp, segs, offs, in, out); };
   // out_j = J^T in_j for the listed slots (at most nbt), other slots zero
   auto applyB = [&](const std::vector<const double*>& in, const std::vector<double*>& out) {
+    std::vector<CopyItem> ci;
     for (size_t i = 0; i < segs.size(); ++i) {
       const Seg& sg = segs[i];
       double* base = c->tp(m.lagB.at(sg.mult));
       for (int j = 0; j < nbt; ++j) {
-        if (j < (int)in.size() && in[j] && sg.active)
-          c->cp(base + (int64_t)j * sg.n, in[j] + offs[i], sg.n);
-        else
-          c->fill(base + (int64_t)j * sg.n, sg.n, 0.0);
+        const bool use = j < (int)in.size() && in[j] && sg.active;
+        ci.push_back({base + (int64_t)j * sg.n, use ? in[j] + offs[i] : nullptr, sg.n});
       }
     }
+    launch_copy_list(ci, c->s);
     c->run(m.p_lagB);
+    std::vector<CopyItem> co;
+    std::vector<double*> sym;
     for (size_t i = 0; i < segs.size(); ++i) {
       const Seg& sg = segs[i];
       auto it = m.lagB.find(sg.adj);
       for (int j = 0; j < (int)out.size(); ++j) {
         if (!out[j]) continue;
         if (!sg.active || it == m.lagB.end()) {
-          c->fill(out[j] + offs[i], sg.n, 0.0);
+          co.push_back({out[j] + offs[i], nullptr, sg.n});
           continue;
         }
-        c->cp(out[j] + offs[i], c->tp(it->second) + (int64_t)j * sg.n, sg.n);
-        if (sg.comp == 2) c->sym_doubles(out[j] + offs[i]);
+        co.push_back({out[j] + offs[i], c->tp(it->second) + (int64_t)j * sg.n, sg.n});
+        if (sg.comp == 2) sym.push_back(out[j] + offs[i]);
       }
     }
+    launch_copy_list(co, c->s);
+    for (double* p : sym) c->sym_doubles(p);
   };
   const int maxg = std::max(c->opt.max_iter, cap);
   std::vector<int> failed;
@@ -2093,6 +2096,15 @@ int scc_profile(scc_ctx* c, int enable, int kernel, double* gemm_ms, double* gem
     if (gemm_flops) *gemm_flops = c->ex->kernel_flops[kernel];
     if (gemm_launches) *gemm_launches = (long long)c->ex->kernel_launches[kernel];
     if (gemm_bytes) *gemm_bytes = c->ex->kernel_bytes[kernel];
+    return SCC_OK;
+  });
+}
+
+int scc_profile_kernels(scc_ctx* c, unsigned mask) {
+  if (!c) return SCC_EINVAL;
+  return guarded(c, nullptr, [&]() -> int {
+    c->ex->flush_profile();
+    c->ex->set_profile_mask(mask);
     return SCC_OK;
   });
 }
