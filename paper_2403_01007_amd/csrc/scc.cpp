@@ -311,6 +311,58 @@ std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, co
   return h;
 }
 
+// Dot products (x . y) and multi-dots (C[i] . r, i < k) queued on the stream
+// and read back with one wait; each result comes from the same kernels as
+// dot() and multi_dot(), so the values are the same.
+struct DotBatch {
+  struct Req {
+    const double* a;
+    int k;  // -1: dot(a, r)
+    const double* r;
+  };
+  std::vector<Req> reqs;
+  int dot(const double* x, const double* y) {
+    reqs.push_back({x, -1, y});
+    return (int)reqs.size() - 1;
+  }
+  int multi(const double* Cb, int k, const double* r) {
+    reqs.push_back({Cb, k, r});
+    return (int)reqs.size() - 1;
+  }
+  // results in request order (a dot gives one value)
+  std::vector<std::vector<double>> run(scc_ctx* c, int64_t n) {
+    std::vector<std::vector<double>> out(reqs.size());
+    int total = 0;
+    for (const Req& q : reqs) total += q.k < 0 ? 1 : q.k;
+    if (total == 0) {
+      reqs.clear();
+      return out;
+    }
+    double* tmp = c->alloc(total);
+    int off = 0;
+    for (const Req& q : reqs) {
+      if (q.k < 0) {
+        launch_dot(q.a, q.r, n, 1.0, nullptr, 0.0, tmp + off, c->partials, c->s);
+        off += 1;
+      } else if (q.k > 0) {
+        launch_deriv_contract(q.a, n, q.r, q.a, 0, q.r, q.k, tmp + off, c->partials, c->s);
+        off += q.k;
+      }
+    }
+    std::vector<double> h(total);
+    c->xfer(h.data(), tmp, total * sizeof(double), hipMemcpyDeviceToHost);
+    c->pool_used -= up(total);
+    off = 0;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+      const int k = reqs[i].k < 0 ? 1 : reqs[i].k;
+      out[i].assign(h.begin() + off, h.begin() + off + k);
+      off += k;
+    }
+    reqs.clear();
+    return out;
+  }
+};
+
 // y += sum_i coef_i X[i] (X [k][n]) in one streaming pass
 void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* devcoef,
                 double* y) {
@@ -447,13 +499,16 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       nw = nv;
     }
     // new rows and columns of the subspace matrix G_ij = V_i . W_j
-    for (int j = ng; j < nv; ++j) {
-      auto col = multi_dot(c, Vb, nv, nvt, W[j]);
-      for (int i = 0; i < nv; ++i) G[i * maxsub + j] = col[i];
-    }
-    for (int i = ng; i < nv; ++i) {
-      auto row = multi_dot(c, Wb, ng, nvt, V[i]);
-      for (int j = 0; j < ng; ++j) G[i * maxsub + j] = row[j];
+    {
+      DotBatch db;
+      for (int j = ng; j < nv; ++j) db.multi(Vb, nv, W[j]);
+      for (int i = ng; i < nv; ++i) db.multi(Wb, ng, V[i]);
+      auto res = db.run(c, nvt);
+      int q = 0;
+      for (int j = ng; j < nv; ++j, ++q)
+        for (int i = 0; i < nv; ++i) G[i * maxsub + j] = res[q][i];
+      for (int i = ng; i < nv; ++i, ++q)
+        for (int j = 0; j < ng; ++j) G[i * maxsub + j] = res[q][j];
     }
     ng = nv;
     std::vector<double> Gs(nv * nv);
@@ -477,7 +532,7 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     }
     double maxres = 0;
     std::vector<double> th(nx);
-    std::vector<char> conv(nx, 0);
+    std::vector<char> conv(nx, 0), cplx_k(nx, 0);
     for (int k = 0; k < nx; ++k) {
       int col = ord[k];
       th[k] = w[col].real();
@@ -499,9 +554,18 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       if (k < nr_now) {
         c->cp(Rs[k], Xw[k], nvt);
         c->axpby(-th[k], Xr[k], 1.0, Rs[k], nvt);
-        double rn = std::sqrt(c->dot(Rs[k], Rs[k], nvt));
+        cplx_k[k] = cplx_pair;
+      }
+    }
+    // residual norms of the working roots, read back together
+    {
+      DotBatch db;
+      for (int k = 0; k < std::min(nr_now, nx); ++k) db.dot(Rs[k], Rs[k]);
+      auto res = db.run(c, nvt);
+      for (int k = 0; k < std::min(nr_now, nx); ++k) {
+        const double rn = std::sqrt(res[k][0]);
         if (k < nroots) maxres = std::max(maxres, rn);
-        conv[k] = rn < tol && !cplx_pair;
+        conv[k] = rn < tol && !cplx_k[k];
       }
     }
     if (c->opt.verbose) {
@@ -1395,9 +1459,14 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
       std::vector<const double*> cin(nb, nullptr);
       std::vector<double*> cout(nb, nullptr);
       bool any = false;
+      DotBatch drr;
+      std::vector<int> irr(nb, -1);
+      for (int j = 0; j < nb; ++j)
+        if (!done[j] && !force[j]) irr[j] = drr.dot(R[j], R[j]);
+      const auto rr = drr.run(c, n);
       for (int j = 0; j < nb; ++j) {
         if (done[j]) continue;
-        const double rel = force[j] ? 0.0 : std::sqrt(c->dot(R[j], R[j], n)) / bn[j];
+        const double rel = force[j] ? 0.0 : std::sqrt(rr[irr[j]][0]) / bn[j];
         if (it % 10 == 0) c->log("  batched gcr it %3d target %d (stored %d)  rel. residual %.3e\n", it, j, k[j], rel);
         if (rel < tol) {
           cin[j] = X[j];
@@ -1439,30 +1508,56 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
       }
       if (!running) break;
       applyB(zin, wout);
-      for (int j = 0; j < nb; ++j) {
-        if (!zin[j]) continue;
-        first[j] = 0;
-        const double w0 = std::sqrt(c->dot(W[j], W[j], n));
-        double wn = w0;
-        for (int pass = 0; pass < 2; ++pass) {
-          const double before = wn;
-          auto be = multi_dot(c, C[j], k[j], n, W[j]);
+      // Orthogonalisation of the new images, all targets at a time: the dot
+      // products of every target are read back with one wait per phase.
+      std::vector<double> w0(nb, 0.0), wn(nb, 0.0);
+      {
+        DotBatch db;
+        std::vector<int> iw(nb, -1), ib(nb, -1);
+        for (int j = 0; j < nb; ++j) {
+          if (!zin[j]) continue;
+          first[j] = 0;
+          iw[j] = db.dot(W[j], W[j]);
+          ib[j] = db.multi(C[j], k[j], W[j]);
+        }
+        auto res = db.run(c, n);
+        for (int j = 0; j < nb; ++j) {
+          if (!zin[j]) continue;
+          w0[j] = std::sqrt(res[iw[j]][0]);
+          auto be = res[ib[j]];
           for (auto& v : be) v = -v;
           multi_axpy(c, C[j], k[j], n, be, cf[j], W[j]);
           multi_axpy(c, U[j], k[j], n, be, cf[j], Z[j]);
-          wn = std::sqrt(c->dot(W[j], W[j], n));
-          if (wn > 0.5 * before) break;
+          iw[j] = db.dot(W[j], W[j]);
         }
-        if (!(wn > 1e-12 * w0)) {
+        res = db.run(c, n);
+        for (int j = 0; j < nb; ++j) {
+          if (!zin[j]) continue;
+          wn[j] = std::sqrt(res[iw[j]][0]);
+          // second pass only where the first one cancelled
+          if (!(wn[j] > 0.5 * w0[j])) {
+            auto be2 = multi_dot(c, C[j], k[j], n, W[j]);
+            for (auto& v : be2) v = -v;
+            multi_axpy(c, C[j], k[j], n, be2, cf[j], W[j]);
+            multi_axpy(c, U[j], k[j], n, be2, cf[j], Z[j]);
+            wn[j] = std::sqrt(c->dot(W[j], W[j], n));
+          }
+        }
+      }
+      DotBatch dal;
+      std::vector<int> ial(nb, -1);
+      for (int j = 0; j < nb; ++j) {
+        if (!zin[j]) continue;
+        if (!(wn[j] > 1e-12 * w0[j])) {
           force[j] = 1;  // invariant space: confirm on the true residual
           continue;
         }
         double* un_ = U[j] + (int64_t)k[j] * n;
         double* cn_ = C[j] + (int64_t)k[j] * n;
         c->cp(un_, Z[j], n);
-        c->axpby(0.0, Z[j], 1.0 / wn, un_, n);
+        c->axpby(0.0, Z[j], 1.0 / wn[j], un_, n);
         c->cp(cn_, W[j], n);
-        c->axpby(0.0, W[j], 1.0 / wn, cn_, n);
+        c->axpby(0.0, W[j], 1.0 / wn[j], cn_, n);
         ++k[j];
         if (reseed[j]) {
           // project the true residual on the whole stored space
@@ -1472,7 +1567,16 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
           multi_axpy(c, C[j], k[j], n, al, cf[j], R[j]);
           reseed[j] = 0;
         } else {
-          const double al = c->dot(cn_, R[j], n);
+          ial[j] = dal.dot(cn_, R[j]);
+        }
+      }
+      {
+        auto res = dal.run(c, n);
+        for (int j = 0; j < nb; ++j) {
+          if (ial[j] < 0) continue;
+          const double al = res[ial[j]][0];
+          double* un_ = U[j] + (int64_t)(k[j] - 1) * n;
+          double* cn_ = C[j] + (int64_t)(k[j] - 1) * n;
           c->axpby(al, un_, 1.0, X[j], n);
           c->axpby(-al, cn_, 1.0, R[j], n);
         }
