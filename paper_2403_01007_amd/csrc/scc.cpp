@@ -317,7 +317,7 @@ std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, co
 struct DotBatch {
   struct Req {
     const double* a;
-    int k;  // -1: dot(a, r)
+    int k;  // -1: dot(a, r); -2: the device value a[0]
     const double* r;
   };
   std::vector<Req> reqs;
@@ -327,6 +327,10 @@ struct DotBatch {
   }
   int multi(const double* Cb, int k, const double* r) {
     reqs.push_back({Cb, k, r});
+    return (int)reqs.size() - 1;
+  }
+  int value(const double* p) {
+    reqs.push_back({p, -2, nullptr});
     return (int)reqs.size() - 1;
   }
   // results in request order (a dot gives one value)
@@ -341,7 +345,10 @@ struct DotBatch {
     double* tmp = c->alloc(total);
     int off = 0;
     for (const Req& q : reqs) {
-      if (q.k < 0) {
+      if (q.k == -2) {
+        c->cp(tmp + off, q.a, 1);
+        off += 1;
+      } else if (q.k < 0) {
         launch_dot(q.a, q.r, n, 1.0, nullptr, 0.0, tmp + off, c->partials, c->s);
         off += 1;
       } else if (q.k > 0) {
@@ -1216,12 +1223,20 @@ void lag_prec(scc_ctx* c, const LagPrec& P, const std::vector<Seg>& segs, const 
       launch_precond(in + offs[i], Dseg, 0.0, 0.05, out + offs[i], sg.n, c->s);
     }
   }
-  // state blocks with their normalisation border
+  // state blocks with their normalisation border (the border values of all
+  // states read back with one wait)
+  DotBatch db;
+  std::vector<int> irf(ns), ig(ns);
   for (int k = 0; k < ns; ++k) {
     const int64_t sb = offs[2 + 4 * k], eb = offs[2 + 4 * k + 3];
     lag_state_dinv(c, k, in + sb, out + sb);
-    const double rf = c->dot(c->R[k], out + sb, nst);
-    const double g = c->host_scalar(in + eb);
+    irf[k] = db.dot(c->R[k], out + sb);
+    ig[k] = db.value(in + eb);
+  }
+  const auto res = db.run(c, nst);
+  for (int k = 0; k < ns; ++k) {
+    const int64_t sb = offs[2 + 4 * k], eb = offs[2 + 4 * k + 3];
+    const double rf = res[irf[k]][0], g = res[ig[k]][0];
     const double mu = std::fabs(P.den[k]) > 1e-300 ? -(g + rf) / P.den[k] : 0.0;
     c->axpby(mu, P.q[k], 1.0, out + sb, nst);
     c->set_scalar_ptr(out + eb, mu);
