@@ -601,8 +601,8 @@ int Graph::fuse_sums(const std::vector<const std::vector<int>*>& programs, const
 }
 
 int64_t Graph::finalize(const std::vector<const std::vector<int>*>& programs, const std::vector<int>& pinned,
-                        int64_t align) {
-  fuse_sums(programs, pinned);
+                        int64_t align, bool fuse) {
+  if (fuse) fuse_sums(programs, pinned);
   auto rnd = [&](int64_t n) { return (n + align - 1) / align * align; };
   const int nt = (int)t.size();
   // owner program of each tensor's producer and of each consumer (-2: several)

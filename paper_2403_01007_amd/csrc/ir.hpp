@@ -123,9 +123,10 @@ class Graph {
   // other tensors get storage of their own.
   // Tensors in `pinned` (read or written by host code) always get storage of
   // their own.
-  // First fuses sums of products (fuse_sums), then assigns storage.
+  // First fuses sums of products (fuse_sums; skipped with fuse = false),
+  // then assigns storage.
   int64_t finalize(const std::vector<const std::vector<int>*>& programs, const std::vector<int>& pinned,
-                   int64_t align = 32);
+                   int64_t align = 32, bool fuse = true);
 
   // Sums of products: where a lincomb adds the outputs of contractions that
   // nothing else reads and whose output indices split the same way between
