@@ -85,6 +85,11 @@ int main(int argc, char** argv) {
   key("E", m.res.E);
   key("O1", m.res.O1);
   key("O2", m.res.O2);
+  auto state = [&](const char* name, int r0, int r1, int r2) { std::fprintf(f, "K %s %d %d %d\n", name, r0, r1, r2); };
+  state("vin", m.vin.r0, m.vin.r1, m.vin.r2);
+  state("sig", m.sig.s0, m.sig.s1, m.sig.s2);
+  state("lin", m.lin.r0, m.lin.r1, m.lin.r2);
+  state("lout", m.lout.r0, m.lout.r1, m.lout.r2);
   for (size_t p = 0; p < m.zeta.size(); ++p) std::fprintf(f, "K zeta%zu %d\n", p, m.zeta[p]);
   for (size_t k = 0; k < m.xs.size(); ++k)
     std::fprintf(f, "K xs%zu %d %d %d\n", k, m.xs[k].r0, m.xs[k].r1, m.xs[k].r2);

@@ -5,7 +5,9 @@ laid out as on the device, so that temporaries share memory exactly as
 there.
 
 - The residual program (after the setup program) matches the oracle's
-  SCCSD residual, with X3 terms (Theory / CC and SCCSD sections).
+  SCCSD residual, with X3 terms (Theory / CC and SCCSD sections); the
+  right transformation matches the oracle's sigma, and the left
+  transformation the oracle's reverse-mode derivative of <l, sigma(r)>.
 - Every program gives the same outputs with and without the fusion of sums
   of products into multi-product contractions, on the same random inputs.
 """
@@ -156,7 +158,7 @@ def _flat(x):
 
 
 @pytest.mark.parametrize("name,ns", [("o2v3", 2), ("custom-o3v6-3", 3)])
-def test_residual_program_matches_oracle(dumper, name, ns):
+def test_residual_and_transformations_match_oracle(dumper, name, ns):
     if name.startswith("custom"):
         S = make_system("custom", seed=17, o=3, v=6, nj=14, nstates=ns, ncoord=1, nacs=[(0, 1)], sf=0.01, sl=0.01)
     else:
@@ -197,6 +199,37 @@ def test_residual_program_matches_oracle(dumper, name, ns):
     assert abs(float(A.view(K["E"][0])) - float(E)) < 1e-11
     np.testing.assert_allclose(A.view(K["O1"][0]), s.numpy(), rtol=0, atol=1e-12)
     np.testing.assert_allclose(A.view(K["O2"][0]), d.numpy(), rtol=0, atol=1e-12)
+
+    # right transformation of one vector (the programs' symmetric doubles)
+    v1, v2 = random_amplitudes(S.o, S.v, seed=31, scale=0.3)
+    vec = (0.7, v1, v2)
+    A.run(g.progs[2])  # sigma: amplitude-only part
+    for i, val in zip(K["vin"], vec):
+        A.set(i, val)
+    A.run(g.progs[3])
+    s0, s1, s2 = cc.sigma(T(h), T(gg), T(t1), T(t2), S.o, T(vec[0]), T(vec[1]), T(vec[2]), T(zeta), rs)
+    out = [A.view(i) for i in K["sig"]]
+    assert abs(float(out[0]) - float(s0)) < 1e-11
+    np.testing.assert_allclose(out[1], s1.numpy(), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out[2], s2.numpy(), rtol=0, atol=1e-12)
+
+    # left transformation: gradient of <l, sigma(r)> with respect to r,
+    # restricted to symmetric doubles
+    l1, l2 = random_amplitudes(S.o, S.v, seed=21, scale=0.3)
+    lvec = (0.4, l1, l2)
+    for i, val in zip(K["lin"], lvec):
+        A.set(i, val)
+    A.run(g.progs[4])
+    r0, r1, r2 = (T(x).requires_grad_(True) for x in vec)
+    q0, q1, q2 = cc.sigma(T(h), T(gg), T(t1), T(t2), S.o, r0, r1, r2, T(zeta), rs)
+    val = T(lvec[0]) * q0 + torch.sum(T(l1) * q1) + torch.sum(T(l2) * q2)
+    g0, g1, g2 = torch.autograd.grad(val, (r0, r1, r2))
+    g2 = 0.5 * (g2 + g2.permute(2, 3, 0, 1))
+    out = [A.view(i) for i in K["lout"]]
+    o2 = 0.5 * (out[2] + out[2].transpose(2, 3, 0, 1))
+    assert abs(float(out[0]) - float(g0)) < 1e-11
+    np.testing.assert_allclose(out[1], g1.numpy(), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(o2, g2.numpy(), rtol=0, atol=1e-12)
 
 
 def test_fused_programs_match_unfused(dumper):
