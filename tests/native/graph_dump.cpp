@@ -90,6 +90,10 @@ int main(int argc, char** argv) {
   state("sig", m.sig.s0, m.sig.s1, m.sig.s2);
   state("lin", m.lin.r0, m.lin.r1, m.lin.r2);
   state("lout", m.lout.r0, m.lout.r1, m.lout.r2);
+  state("vinB", m.vinB.r0, m.vinB.r1, m.vinB.r2);
+  state("sigB", m.sigB.r0, m.sigB.r1, m.sigB.r2);
+  state("linB", m.linB.r0, m.linB.r1, m.linB.r2);
+  state("loutB", m.loutB.r0, m.loutB.r1, m.loutB.r2);
   for (size_t p = 0; p < m.zeta.size(); ++p) std::fprintf(f, "K zeta%zu %d\n", p, m.zeta[p]);
   for (size_t k = 0; k < m.xs.size(); ++k)
     std::fprintf(f, "K xs%zu %d %d %d\n", k, m.xs[k].r0, m.xs[k].r1, m.xs[k].r2);

@@ -232,6 +232,54 @@ def test_residual_and_transformations_match_oracle(dumper, name, ns):
     np.testing.assert_allclose(o2, g2.numpy(), rtol=0, atol=1e-12)
 
 
+def test_batched_transformations_match_single(dumper):
+    """Every slot of the batched right and left transformations (leading
+    batch index Z) equals the single-vector program on that slot's vector."""
+    S = make_system("custom", seed=17, o=3, v=6, nj=14, nstates=2, ncoord=1, nacs=[(0, 1)], sf=0.01, sl=0.01)
+    ns = 2
+    g = dumper(S.o, S.v, S.nj, ns, True)
+    K = g.keys
+    h, L = S.at(np.zeros(S.ncoord))
+    N = S.o + S.v
+    A = Arena(g)
+    A.set(K["In"][0], np.eye(N))
+    A.set(K["Io"][0], np.eye(S.o))
+    A.set(K["one"][0], 1.0)
+    if not g.t[K["z2"][0]]["zero"]:
+        A.set(K["z2"][0], 0.0)
+    A.set(K["h"][0], h)
+    A.set(K["L"][0], L)
+    A.set(K["kappa"][0], 0.0)
+    A.run(g.progs[0])
+    t1, t2 = random_amplitudes(S.o, S.v, seed=5, scale=0.05)
+    A.set(K["t1"][0], t1)
+    A.set(K["t2"][0], t2)
+    amps = random_amplitudes(S.o, S.v, seed=9, scale=0.3, nvec=ns)
+    A.set(K["zeta0"][0], 0.41)
+    for k in range(ns):
+        for i, val in zip(K[f"xs{k}"], (0.3 - 0.2 * k, amps[k][0], amps[k][1])):
+            if not g.t[i]["zero"]:
+                A.set(i, val)
+    A.run(g.progs[1])
+    A.run(g.progs[2])
+    nb = g.t[K["vinB"][0]]["dims"][0]
+    vecs = random_amplitudes(S.o, S.v, seed=44, scale=0.3, nvec=nb)
+    r0s = 0.1 + 0.2 * np.arange(nb)
+    for single, batched, prog, progB, outs, outsB in (("vin", "vinB", 3, 12, "sig", "sigB"),
+                                                      ("lin", "linB", 4, 13, "lout", "loutB")):
+        for i, val in zip(K[batched], (r0s, np.stack([x[0] for x in vecs]), np.stack([x[1] for x in vecs]))):
+            A.set(i, val)
+        A.run(g.progs[progB])
+        got = [A.view(i).copy() for i in K[outsB]]
+        for j in range(nb):
+            for i, val in zip(K[single], (r0s[j], vecs[j][0], vecs[j][1])):
+                A.set(i, val)
+            A.run(g.progs[prog])
+            for q, i in enumerate(K[outs]):
+                ref = A.view(i)
+                np.testing.assert_allclose(got[q][j], ref, rtol=0, atol=1e-12 * max(1.0, float(np.abs(ref).max())))
+
+
 def test_fused_programs_match_unfused(dumper):
     o, v, nj, ns = 3, 8, 16, 3
     gf, gu = dumper(o, v, nj, ns, True), dumper(o, v, nj, ns, False)
