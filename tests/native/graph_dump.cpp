@@ -95,6 +95,9 @@ int main(int argc, char** argv) {
   state("linB", m.linB.r0, m.linB.r1, m.linB.r2);
   state("loutB", m.loutB.r0, m.loutB.r1, m.loutB.r2);
   for (size_t p = 0; p < m.zeta.size(); ++p) std::fprintf(f, "K zeta%zu %d\n", p, m.zeta[p]);
+  // multiplier inputs and adjoint outputs of the Lagrangian product and
+  // their batched copies
+  for (auto& kv : m.lagB) std::fprintf(f, "B %d %d\n", kv.first, kv.second);
   for (size_t k = 0; k < m.xs.size(); ++k)
     std::fprintf(f, "K xs%zu %d %d %d\n", k, m.xs[k].r0, m.xs[k].r1, m.xs[k].r2);
   std::fprintf(f, "H %zu", pinned.size());

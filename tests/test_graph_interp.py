@@ -86,6 +86,9 @@ class Graph:
                 self.pinned = [int(x) for x in w[2:]]
             elif tag == "K":
                 self.keys[w[1]] = [int(x) for x in w[2:]]
+            elif tag == "B":
+                self.batched = getattr(self, "batched", {})
+                self.batched[int(w[1])] = int(w[2])
 
     def produced(self, prog):
         return {self.ops[k][1] for k in prog if self.ops[k][0] != "N"}
@@ -278,6 +281,41 @@ def test_batched_transformations_match_single(dumper):
             for q, i in enumerate(K[outs]):
                 ref = A.view(i)
                 np.testing.assert_allclose(got[q][j], ref, rtol=0, atol=1e-12 * max(1.0, float(np.abs(ref).max())))
+
+
+def test_batched_lagrangian_matches_single(dumper):
+    """Every slot of the batched Lagrangian product (all multiplier targets
+    in lockstep) equals the single-target program on that slot's inputs."""
+    g = dumper(3, 8, 16, 3, True)
+    P_LAG_PRE, P_LAG, P_LAGB = 7, 8, 17
+    pre, lag, lagB = g.progs[P_LAG_PRE], g.progs[P_LAG], g.progs[P_LAGB]
+    A = Arena(g)
+    rng = np.random.default_rng(77)
+    produced = g.produced(pre) | g.produced(lag) | g.produced(lagB)
+    shared = sorted((g.read(pre) | g.read(lag) | g.read(lagB)) - produced)
+    bmap = g.batched
+    batched_in = {b for s, b in bmap.items() if b in g.read(lagB) and b not in g.produced(lagB)}
+    for i in shared:
+        if g.t[i]["zero"] or i in batched_in:
+            continue
+        A.set(i, 0.3 * rng.normal(size=g.t[i]["dims"]))
+    A.run(pre)
+    ins = {s: b for s, b in bmap.items() if b in batched_in}
+    outs = {s: b for s, b in bmap.items() if b in g.produced(lagB)}
+    assert ins and outs
+    for s, b in ins.items():
+        A.set(b, 0.3 * rng.normal(size=g.t[b]["dims"]))
+    A.run(lagB)
+    got = {s: A.view(b).copy() for s, b in outs.items()}
+    nb = next(iter(got.values())).shape[0]
+    for j in range(nb):
+        for s, b in ins.items():
+            A.set(s, A.view(b)[j])
+        A.run(lag)
+        for s in outs:
+            ref = A.view(s)
+            scale = max(1.0, float(np.abs(ref).max()))
+            assert np.abs(got[s][j] - ref).max() <= 1e-11 * scale, (j, s)
 
 
 def test_fused_programs_match_unfused(dumper):
