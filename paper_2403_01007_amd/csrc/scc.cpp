@@ -89,7 +89,6 @@ struct Recycler {
   int cap = 0, k = 0;
   double* U = nullptr;     // [cap][n] search directions
   double* C = nullptr;     // [cap][n] their images, orthonormal
-  double* coef = nullptr;  // [cap] device scratch
   void reset() { k = 0; }
 };
 
@@ -132,7 +131,6 @@ struct scc_ctx {
   bool fixed_basis = false;   // Hamiltonian (and derivative integrals) in a fixed basis
   int last_ground_its = 0;    // iterations of the last ground-state solve
   double* krylov = nullptr;   // Krylov region of the multiplier solves
-  double* batch_coef = nullptr;
   double* batch_vec = nullptr;
   double E0 = 0.0, enuc = 0.0;
   std::vector<double> E, zeta;
@@ -371,10 +369,8 @@ struct DotBatch {
 };
 
 // y += sum_i coef_i X[i] (X [k][n]) in one streaming pass
-void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* devcoef,
-                double* y) {
+void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* y) {
   if (k == 0) return;
-  (void)devcoef;
   launch_combine(Xb, k, n, coef.data(), y, c->s);
 }
 
@@ -453,7 +449,6 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     V[i] = Vb + (int64_t)i * nvt;
     W[i] = Wb + (int64_t)i * nvt;
   }
-  double* dcoef = c->alloc(maxsub);
   std::vector<double*> Xr(nkeep), Xw(nkeep), Rs(nwork);
   for (int i = 0; i < nkeep; ++i) {
     Xr[i] = c->alloc(nvt);
@@ -469,7 +464,7 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     for (int pass = 0; pass < 2; ++pass) {
       auto h = multi_dot(c, Vb, nv, nvt, src);
       for (auto& x : h) x = -x;
-      multi_axpy(c, Vb, nv, nvt, h, dcoef, src);
+      multi_axpy(c, Vb, nv, nvt, h, src);
     }
     double nr = std::sqrt(c->dot(src, src, nvt));
     if (nr < 1e-8) return false;
@@ -556,8 +551,8 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       c->fill(Xr[k], nvt, 0.0);
       c->fill(Xw[k], nvt, 0.0);
       for (auto& yy : y) yy /= yn;
-      multi_axpy(c, Vb, nv, nvt, y, dcoef, Xr[k]);
-      multi_axpy(c, Wb, nv, nvt, y, dcoef, Xw[k]);
+      multi_axpy(c, Vb, nv, nvt, y, Xr[k]);
+      multi_axpy(c, Wb, nv, nvt, y, Xw[k]);
       if (k < nr_now) {
         c->cp(Rs[k], Xw[k], nvt);
         c->axpby(-th[k], Xr[k], 1.0, Rs[k], nvt);
@@ -598,8 +593,8 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
         for (int pass = 0; pass < 2; ++pass) {
           auto h = multi_dot(c, Vb, nv, nvt, Xr[k]);
           for (auto& x : h) x = -x;
-          multi_axpy(c, Vb, nv, nvt, h, dcoef, Xr[k]);
-          multi_axpy(c, Wb, nv, nvt, h, dcoef, Xw[k]);
+          multi_axpy(c, Vb, nv, nvt, h, Xr[k]);
+          multi_axpy(c, Wb, nv, nvt, h, Xw[k]);
         }
         double nr = std::sqrt(c->dot(Xr[k], Xr[k], nvt));
         if (nr < 1e-8) continue;
@@ -1003,9 +998,9 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
   rc.reset();
   if (rc.k > 0) {
     auto al = multi_dot(c, rc.C, rc.k, n, r);
-    multi_axpy(c, rc.U, rc.k, n, al, rc.coef, x);
+    multi_axpy(c, rc.U, rc.k, n, al, x);
     for (auto& v : al) v = -v;
-    multi_axpy(c, rc.C, rc.k, n, al, rc.coef, r);
+    multi_axpy(c, rc.C, rc.k, n, al, r);
   }
   int checks = 0;
   for (int it = 0; it < maxit; ++it) {
@@ -1031,8 +1026,8 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
       for (int pass = 0; pass < 2; ++pass) {
         auto be = multi_dot(c, rc.C, rc.k, n, w);
         for (auto& v : be) v = -v;
-        multi_axpy(c, rc.C, rc.k, n, be, rc.coef, w);
-        multi_axpy(c, rc.U, rc.k, n, be, rc.coef, z);
+        multi_axpy(c, rc.C, rc.k, n, be, w);
+        multi_axpy(c, rc.U, rc.k, n, be, z);
       }
       double wn = std::sqrt(c->dot(w, w, n));
       if (!(wn > 0) || rc.k >= rc.cap) break;
@@ -1045,9 +1040,9 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
       ++rc.k;
       // project the true residual on the whole stored space
       auto al = multi_dot(c, rc.C, rc.k, n, r);
-      multi_axpy(c, rc.U, rc.k, n, al, rc.coef, x);
+      multi_axpy(c, rc.U, rc.k, n, al, x);
       for (auto& v : al) v = -v;
-      multi_axpy(c, rc.C, rc.k, n, al, rc.coef, r);
+      multi_axpy(c, rc.C, rc.k, n, al, r);
       continue;
     }
     if (rc.k >= rc.cap) break;
@@ -1069,8 +1064,8 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
       auto be = multi_dot(c, rc.C, rc.k, n, w);
       std::vector<double> nb(be.size());
       for (size_t i = 0; i < be.size(); ++i) nb[i] = -be[i];
-      multi_axpy(c, rc.C, rc.k, n, nb, rc.coef, w);
-      multi_axpy(c, rc.U, rc.k, n, nb, rc.coef, z);
+      multi_axpy(c, rc.C, rc.k, n, nb, w);
+      multi_axpy(c, rc.U, rc.k, n, nb, z);
       wn = std::sqrt(c->dot(w, w, n));
       if (wn > 0.5 * before) break;
     }
@@ -1448,7 +1443,7 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
   std::vector<int> failed;
   for (size_t b0 = 0; b0 < tg.size(); b0 += nbt) {
     const int nb = (int)std::min<size_t>(nbt, tg.size() - b0);
-    std::vector<double*> B(nb), X(nb), R(nb), Z(nb), W(nb), U(nb), C(nb), cf(nb);
+    std::vector<double*> B(nb), X(nb), R(nb), Z(nb), W(nb), U(nb), C(nb);
     std::vector<int> k(nb, 0), done(nb, 0), checks(nb, 0);
     std::vector<char> first(nb, 1), reseed(nb, 0), force(nb, 0);
     std::vector<double> bn(nb);
@@ -1460,7 +1455,6 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
       W[j] = c->batch_vec + (4 * (int64_t)nbt + j) * un;
       U[j] = c->krylov + (2 * (int64_t)j) * cap * un;
       C[j] = c->krylov + (2 * (int64_t)j + 1) * cap * un;
-      cf[j] = c->batch_coef + (int64_t)j * up(cap);
       const Target& t = tg[b0 + j];
       lag_rhs(c, offs, t.kind, t.m, t.n, B[j]);
       c->fill(X[j], n, 0.0);
@@ -1541,8 +1535,8 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
           w0[j] = std::sqrt(res[iw[j]][0]);
           auto be = res[ib[j]];
           for (auto& v : be) v = -v;
-          multi_axpy(c, C[j], k[j], n, be, cf[j], W[j]);
-          multi_axpy(c, U[j], k[j], n, be, cf[j], Z[j]);
+          multi_axpy(c, C[j], k[j], n, be, W[j]);
+          multi_axpy(c, U[j], k[j], n, be, Z[j]);
           iw[j] = db.dot(W[j], W[j]);
         }
         res = db.run(c, n);
@@ -1553,8 +1547,8 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
           if (!(wn[j] > 0.5 * w0[j])) {
             auto be2 = multi_dot(c, C[j], k[j], n, W[j]);
             for (auto& v : be2) v = -v;
-            multi_axpy(c, C[j], k[j], n, be2, cf[j], W[j]);
-            multi_axpy(c, U[j], k[j], n, be2, cf[j], Z[j]);
+            multi_axpy(c, C[j], k[j], n, be2, W[j]);
+            multi_axpy(c, U[j], k[j], n, be2, Z[j]);
             wn[j] = std::sqrt(c->dot(W[j], W[j], n));
           }
         }
@@ -1577,9 +1571,9 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
         if (reseed[j]) {
           // project the true residual on the whole stored space
           auto al = multi_dot(c, C[j], k[j], n, R[j]);
-          multi_axpy(c, U[j], k[j], n, al, cf[j], X[j]);
+          multi_axpy(c, U[j], k[j], n, al, X[j]);
           for (auto& v : al) v = -v;
-          multi_axpy(c, C[j], k[j], n, al, cf[j], R[j]);
+          multi_axpy(c, C[j], k[j], n, al, R[j]);
           reseed[j] = 0;
         } else {
           ial[j] = dal.dot(cn_, R[j]);
@@ -1758,14 +1752,11 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     c->krylov = c->alloc(c->sz.krylov);
     c->rec_lag.U = c->krylov;
     c->rec_lag.C = c->krylov + (int64_t)c->sz.cap_lag * up(c->sz.nlag);
-    c->rec_lag.coef = c->alloc(c->sz.cap_lag);
-    c->batch_coef = c->alloc((int64_t)c->sz.nbt * up(c->sz.cap_b));
     c->batch_vec = c->alloc(5 * (int64_t)c->sz.nbt * up(c->sz.nlag));
     c->rec_k.n = c->sz.nov;
     c->rec_k.cap = c->sz.cap_k;
     c->rec_k.U = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
     c->rec_k.C = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
-    c->rec_k.coef = c->alloc(c->sz.cap_k);
     // constants
     Model& m = c->m;
     std::vector<double> In((size_t)dd.n * dd.n, 0.0), Io((size_t)dd.o * dd.o, 0.0);
