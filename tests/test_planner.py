@@ -27,7 +27,9 @@ def checker(tmp_path_factory):
     return exe
 
 
-@pytest.mark.parametrize("dims", [(2, 4, 12, 3), (4, 12, 40, 3), (5, 19, 60, 3), (3, 9, 20, 2)])
+@pytest.mark.parametrize("dims", [(2, 4, 12, 3), (4, 12, 40, 3), (5, 19, 60, 3), (3, 9, 20, 2),
+                                  (10, 90, 300, 3)],  # the o10v90 workload bench.py times (about a minute)
+                         ids=["o2v4", "o4v12", "o5v19", "o3v9", "o10v90"])
 def test_gemm_address_maps_are_bijections(checker, dims):
     r = subprocess.run([checker] + [str(x) for x in dims], capture_output=True, text=True, timeout=600)
     print(r.stdout)
