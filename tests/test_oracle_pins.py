@@ -6,6 +6,9 @@
   equal Hellmann-Feynman FCI values, couplings equal
   <psi_m|H^(1)|psi_n>/(E_n - E_m);
 * SCCSD gradients equal 5-point central differences of the SCCSD energies;
+* SCCSD couplings equal 5-point central differences of the bra-frozen
+  overlap built in the determinant space, with the orbitals at the displaced
+  geometry reached by the exact orbital rotation (no multipliers involved);
 * closed forms of the Lagrangian (K-vectors and Lbar_0, gradient/coupling
   stationarity sections).
 """
@@ -158,6 +161,44 @@ def test_scc_gradient_matches_finite_differences(o2v4_solution):
         fd = (E[-2] - 8 * E[-1] + 8 * E[1] - E[2]) / (12 * step)
         for n in range(2):
             assert abs(fd[n] - res[("grad", n)]["value"][c]) < 1e-8
+
+
+def test_scc_coupling_matches_finite_differences(o2v4_solution):
+    """d_mn[c] = dO_mn/dx_c at x0 with O_mn(x) = <calL_m(x0)| exp(-T0)
+    exp(-kappa(x)) exp(T(x)) |calR_n(x)> (derivative on the ket,
+    coupling section), evaluated from definitions in the determinant space:
+    the displaced solution (RHF and SCC re-solved, continued from x0) is
+    mapped to the x0 orbitals by the Fock-space rotation exp(sum_pq A_pq E_pq),
+    A = log of the orbital rotation C(x0)^T C(x) (C(x0) = 1 here), then
+    exp(-T0) and the projection onto the excitation space are applied and the
+    x0 left vector is contracted.  5-point differences, h = 1e-3."""
+    import scipy.linalg as sla
+    S, sol, res = o2v4_solution
+    m, n = 0, 1
+    lag = scc.Lagrangian(sol)
+    fs = FockSpace(S.o + S.v, S.o)
+    back = sla.expm(-fs.cluster_op(sol.t1.numpy(), sol.t2.numpy()))
+
+    def overlap(x):
+        sx = scc.solve_system(S, x=x, start=sol)
+        A = np.real(sla.logm(np.asarray(sx.C)))
+        rot = sla.expm(np.einsum("pq,pqIJ->IJ", A, fs.E))
+        r = sx.R[n]
+        ket = sla.expm(fs.cluster_op(sx.t1.numpy(), sx.t2.numpy())) @ fs.vector(
+            float(r[0]), np.asarray(r[1]), np.asarray(r[2]))
+        c0, c1, c2 = fs.coefficients(back @ rot @ ket)
+        return float(lag.Lam[m] @ torch.cat([T([c0]), lag.P.pack(T(c1), T(c2))]))
+
+    assert abs(overlap(np.zeros(S.ncoord))) < 1e-10  # <calL_m|calR_n> = 0
+    step = 1e-3
+    for c in range(S.ncoord):
+        O = {}
+        for st in (-2, -1, 1, 2):
+            x = np.zeros(S.ncoord)
+            x[c] = st * step
+            O[st] = overlap(x)
+        fd = (O[-2] - 8 * O[-1] + 8 * O[1] - O[2]) / (12 * step)
+        assert abs(fd - res[("nac", m, n)]["value"][c]) < 1e-8
 
 
 def test_lagrangian_closed_forms(o2v4_solution):
