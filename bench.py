@@ -5,8 +5,14 @@ bounded sample.  Prints one JSON line.
 
 Workload (default o10v90): synthetic Cholesky-factored Hamiltonian with
 o = 10, v = 90, N_J = 300, 3 excited states, 36 coordinates, 3 pairwise
-couplings; per step: set Hamiltonian (cold start), SCCSD(E) ground + excited
-states, gradients of all 3 states, 3 couplings over all coordinates.
+couplings.  One step is one geometry x of the trajectory family
+H(x) = H0 + sum_k x_k H_k (x_k ~ N(0, 0.05^2), a new x every step, H(x)
+already on the device): RHF in the fixed basis and MO transformation on the
+device, SCCSD(E) ground + excited states from a cold start, gradients of all
+3 states and 3 couplings over all coordinates.
+
+The warm-up and timed loops stop early at their wall budgets (--warmup-budget,
+--budget, seconds): the JSON line reports the steps actually run.
 """
 import argparse
 import json
@@ -207,8 +213,13 @@ def learned_main(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--budget", type=float, default=120.0,
+                    help="wall budget (s) of the timed loop: no step starts that would end past it (at least one "
+                         "step runs)")
+    ap.add_argument("--warmup-budget", type=float, default=60.0,
+                    help="wall budget (s) of the warm-up loop (at least one warm-up step runs when --warmup > 0)")
     ap.add_argument("--workload", default="o10v90")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="fp32: FP32 products in the dense contractions, then FP64 refinement")
@@ -247,11 +258,19 @@ def main():
         return
     from paper_2403_01007_amd import Context
     from paper_2403_01007_amd.binding import GEMM_KERNEL_NAMES
-    from synth_inputs import make_system
+    from synth_inputs import family_geometries, make_system
 
     S = make_system(args.workload)
     h, L = S.at(np.zeros(S.ncoord))
     dev = torch.device("cuda:0")
+    # one geometry of the trajectory family per step, H(x) formed and moved to
+    # the device before the timed region (held-out seeds 20000+)
+    nstep_max = args.warmup + args.steps
+    geoms = family_geometries(S.ncoord, range(20000, 20000 + nstep_max))
+    HX = []
+    for x in geoms:
+        hx, Lx = S.at(x)
+        HX.append((torch.as_tensor(hx, device=dev), torch.as_tensor(Lx, device=dev)))
     ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11, verbose=args.verbose,
                   precision=args.precision, eager=args.eager)
     h_d = torch.as_tensor(h, device=dev)
@@ -266,8 +285,10 @@ def main():
             print(f"[phase {name}: {info.seconds:.2f} s, {info.iterations} iterations, "
                   f"{info.flops_mfma / 1e12:.2f} TFLOP]", file=sys.stderr, flush=True)
 
-    def step(ctx=ctx):
-        ctx.set_hamiltonian(h_d, L_d)
+    def step(i, ctx=ctx):
+        hx, Lx = HX[i]
+        _, info = ctx.set_hamiltonian_fixed_basis(hx, Lx)
+        phase("rhf", info)
         E, zeta, info = ctx.excited()
         phase("excited", info)
         out = {"E": E, "zeta": zeta}
@@ -293,7 +314,7 @@ def main():
     if args.precision == "fp32" and args.compare_fp64:
         ref_ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11, verbose=args.verbose)
         r0 = time.perf_counter()
-        reference = step(ref_ctx)
+        reference = step(args.warmup, ref_ctx)
         torch.cuda.synchronize()
         reference["seconds"] = time.perf_counter() - r0
         ref_ctx.close()
@@ -305,9 +326,18 @@ def main():
     # load the kernels and touch every code path once outside the timed region
     ctx.set_hamiltonian(h_d, L_d)
     ctx.eval_residual(np.zeros(S.o * S.v * (1 + S.o * S.v)))
-    for _ in range(args.warmup):
-        step()
-        print(f"[warmup step done]", file=sys.stderr, flush=True)
+    # warm-up: no step starts that would end past the warm-up budget
+    warm_run = 0
+    w0 = time.perf_counter()
+    for i in range(args.warmup):
+        s0 = time.perf_counter()
+        step(i)
+        torch.cuda.synchronize()
+        warm_run += 1
+        last = time.perf_counter() - s0
+        print(f"[warmup step {i} done: {last:.1f} s]", file=sys.stderr, flush=True)
+        if time.perf_counter() - w0 + last > args.warmup_budget:
+            break
     flops[0] = 0.0
     kernels = range(len(GEMM_KERNEL_NAMES))
     # events on the multi-product GEMM launches only (the dominant kernel by
@@ -318,13 +348,20 @@ def main():
     before = [ctx.profile(not args.no_roofline, q) for q in kernels]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    steps_run = 0
     for k in range(args.steps):
-        res = step()
-        print(f"[timed step {k} done]", file=sys.stderr, flush=True)
+        s0 = time.perf_counter()
+        res = step(args.warmup + k)
+        torch.cuda.synchronize()
+        steps_run += 1
+        last = time.perf_counter() - s0
+        print(f"[timed step {k} done: {last:.1f} s]", file=sys.stderr, flush=True)
+        if time.perf_counter() - t0 + last > args.budget:
+            break
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     after = [ctx.profile(False, q) for q in kernels]
-    s_per_geom = elapsed / args.steps
+    s_per_geom = elapsed / steps_run
     # per GEMM kernel over the timed steps: seconds, flops, launches; the
     # roofline is that of the kernel with the most time
     per_kernel = {GEMM_KERNEL_NAMES[q]: ((after[q][0] - before[q][0]) / 1e3, after[q][1] - before[q][1],
@@ -362,7 +399,7 @@ def main():
             tc += time.perf_counter() - c0
             nrep += 1
         per_res = tc / nrep
-        equiv = (flops[0] / args.steps) / res_flops if res_flops > 0 else float("nan")
+        equiv = (flops[0] / steps_run) / res_flops if res_flops > 0 else float("nan")
         cpu = {"value": per_res * equiv, "unit": "s/geometry", "cores": threads, "kind": "oracle",
                "sample": (f"{nrep} oracle CCSD residual evaluations at {args.workload} "
                           f"({per_res:.2f} s each, full N^4 integrals, torch CPU FP64), scaled by the "
@@ -370,13 +407,14 @@ def main():
 
     line = {
         "metric": "s/geometry (energies+gradients+NACs), MFMA TFLOP/s; mixed+learned vs FP64",
-        "value": s_per_geom, "unit": "s/geometry", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": s_per_geom, "unit": "s/geometry", "n_gpus": 1, "steps": steps_run, "warmup": warm_run,
+        "steps_requested": args.steps, "warmup_requested": args.warmup,
         "ms_per_step": 1e3 * s_per_geom, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32-products+f64", "data": "synthetic",
         "config": {"workload": args.workload, "o": S.o, "v": S.v, "nchol": S.nj, "nstates": S.nstates,
                    "ncoord": S.ncoord, "nacs": len(S.nacs), "precision": args.precision, "guess": "mp2/unit",
                    "generator": S.reading},
-        "tflops_contractions": (flops[0] / args.steps) / s_per_geom / 1e12,
+        "tflops_contractions": (flops[0] / steps_run) / s_per_geom / 1e12,
         "roofline": {"bound": "mfma", "kernel": top, "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic, "launches": gemm_n, "kernel_seconds": gemm_s,

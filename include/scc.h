@@ -92,7 +92,11 @@ typedef struct scc_info {
   int fallback_used;     /* 1 if a supplied guess was rejected */
   double residual;       /* final residual norm */
   double seconds;        /* wall time of the call */
-  double flops_mfma;     /* FP64 contraction flops executed by the call */
+  double flops_mfma;     /* contraction flops executed by the call */
+  int precision;         /* 0: every contraction of the call took FP64
+                            products; 1: part of the call ran with
+                            reduced-precision products (options.precision =
+                            1) before its FP64 refinement */
 } scc_info;
 
 typedef struct scc_ctx scc_ctx;
@@ -110,9 +114,13 @@ void scc_destroy(scc_ctx* ctx);
 /* Message of the last failure of this context (host string, owned by ctx). */
 const char* scc_last_error(const scc_ctx* ctx);
 
-/* Hamiltonian of the current geometry in its canonical restricted
- * Hartree-Fock molecular-orbital basis (orbital energies ascending within
- * the occupied and the virtual blocks):
+/* Hamiltonian of the current geometry (Theory, coupled cluster section: the
+ * electronic Hamiltonian in second quantization, one-electron integrals h_pq
+ * with the singlet excitation operators E_pq and two-electron integrals
+ * g_pqrs with e_pqrs, plus the nuclear repulsion e_nuc; the same H enters the
+ * transition-density form of <L|Hbar^(1)|R> in the gradient section) in its
+ * canonical restricted Hartree-Fock molecular-orbital basis (orbital
+ * energies ascending within the occupied and the virtual blocks):
  *   h    [N][N]         one-electron integrals,
  *   chol [N_J][N][N]    Cholesky vectors, symmetric in the last two indices.
  * Copies into the workspace; invalidates every cached solution and resets
@@ -168,10 +176,23 @@ int scc_excited(scc_ctx* ctx, int nstates, const double* guess, double* energies
  * orthogonality multipliers first, then the orbital multipliers. */
 int scc_multipliers(scc_ctx* ctx, int kind, int m, int n, scc_info* info);
 
-/* Effective densities of the last multiplier solve: d1 [N][N] = dL/dh,
- * z3 [N_J][N][N] = dL/dL^J (MO basis, or the fixed basis after
- * scc_set_hamiltonian_fixed_basis), kappa_bar [v][o].  Any may be NULL. */
-int scc_densities(scc_ctx* ctx, double* d1, double* z3, double* kappa_bar);
+/* Effective densities of one target: the gradient of state n (kind = 0, m
+ * ignored) or the coupling d_mn (kind = 1).  They are the one- and
+ * two-electron densities that the gradient and coupling expressions
+ * (eqs. gradient_expression, coupling_expression) contract with the
+ * derivative Hamiltonian: the transition densities d_pq, d_pqrs of the
+ * effective bras K_k (eqs. K-gradients, K-couplings) with the right states,
+ * plus those of L0-bar^k with calR_k and of zeta-bar with HF, plus the orbital
+ * multipliers kappa-bar, which contract with F_ai^(1).  With Cholesky
+ * integrals the two-electron part is returned factorised:
+ *   d1 [N][N]          = dL/dh_pq,
+ *   z3 [N_J][N][N]     = dL/dL^J_pq  (= 2 sum_rs d_pqrs L^J_rs, symmetrised),
+ *   kappa_bar [v][o]   orbital multipliers,
+ * in the MO basis, or the fixed basis after scc_set_hamiltonian_fixed_basis.
+ * Any output may be NULL.  Solves the target's multipliers first unless they
+ * are those of the last scc_multipliers / scc_gradient / scc_nac call.
+ * SCC_EINVAL for a bad target; SCC_ESTATE before scc_excited. */
+int scc_densities(scc_ctx* ctx, int kind, int m, int n, double* d1, double* z3, double* kappa_bar);
 
 /* Gradient g_n (eq. gradient_expression) along ncoord coordinates whose
  * derivative integrals, in the same MO basis, are dh [ncoord][N][N] and

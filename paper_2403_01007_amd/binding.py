@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("fallback_used", ctypes.c_int),
-                ("residual", ctypes.c_double), ("seconds", ctypes.c_double), ("flops_mfma", ctypes.c_double)]
+                ("residual", ctypes.c_double), ("seconds", ctypes.c_double), ("flops_mfma", ctypes.c_double),
+                ("precision", ctypes.c_int)]
 
 
 class MlpDims(ctypes.Structure):
@@ -75,7 +76,7 @@ def load_library():
     lib.scc_ground.argtypes = [P, P, P, ctypes.POINTER(Info)]
     lib.scc_excited.argtypes = [P, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_multipliers.argtypes = [P, I, I, I, ctypes.POINTER(Info)]
-    lib.scc_densities.argtypes = [P, P, P, P]
+    lib.scc_densities.argtypes = [P, I, I, I, P, P, P]
     lib.scc_gradient.argtypes = [P, I, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_nac.argtypes = [P, I, I, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_get.argtypes = [P, I, I, P]
@@ -213,11 +214,13 @@ class Context:
         self._check(self.lib.scc_multipliers(self.h, kind, m, n, ctypes.byref(info)), "scc_multipliers")
         return info
 
-    def densities(self):
+    def densities(self, kind, m, n):
+        """Effective densities of the gradient of state n (kind 0) or of the
+        coupling d_mn (kind 1): (d1 [N][N], z3 [N_J][N][N], kappa_bar [v][o])."""
         d1 = self.zeros(self.n, self.n)
         z3 = self.zeros(self.nj, self.n, self.n)
         kb = self.zeros(self.v, self.o)
-        self._check(self.lib.scc_densities(self.h, _ptr(d1), _ptr(z3), _ptr(kb)), "scc_densities")
+        self._check(self.lib.scc_densities(self.h, kind, m, n, _ptr(d1), _ptr(z3), _ptr(kb)), "scc_densities")
         return d1, z3, kb
 
     def gradient(self, n, dh, dchol):

@@ -115,6 +115,12 @@ struct scc_ctx {
   double* partials = nullptr;
   double* pool = nullptr;
   int64_t pool_used = 0;
+  int64_t pool_base = 0;      // pool in use between calls (context-lifetime vectors)
+  bool used_lowp = false;     // reduced-precision products ran during the current call
+  void set_lowp(bool on) {
+    ex->set_lowp(on);
+    if (on) used_lowp = true;
+  }
   scc_options opt{};
   std::string err;
   // persistent device vectors
@@ -203,6 +209,17 @@ struct scc_ctx {
   void log(const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 };
 
+// Scoped use of the solver pool: everything allocated after construction is
+// released when the scope ends, on every return and throw.
+struct PoolMark {
+  scc_ctx* c;
+  int64_t mark;
+  explicit PoolMark(scc_ctx* cc) : c(cc), mark(cc->pool_used) {}
+  ~PoolMark() { c->pool_used = mark; }
+  PoolMark(const PoolMark&) = delete;
+  PoolMark& operator=(const PoolMark&) = delete;
+};
+
 void scc_ctx::log(const char* fmt, ...) {
   if (!opt.verbose) return;
   va_list ap;
@@ -220,7 +237,7 @@ namespace {
 int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
   Model& m = c->m;
   const int64_t nvt = c->sz.nvt, nov = c->sz.nov;
-  int64_t mark = c->pool_used;
+  PoolMark pm(c);
   double* x = c->alloc(nvt);
   double* r = c->alloc(nvt);
   double* e = c->alloc(nvt);
@@ -287,7 +304,6 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
   c->put(m.t1, x);
   c->put(m.t2, x + nov);
   c->run(m.p_res);
-  c->pool_used = mark;
   if (it >= maxit) {
     c->err = "ground-state iterations did not converge";
     return SCC_ENOCONV;
@@ -299,13 +315,10 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
 std::vector<double> multi_dot(scc_ctx* c, const double* Cb, int k, int64_t n, const double* r) {
   std::vector<double> h(k);
   if (k == 0) return h;
-  double* dout = c->dsc + 16;
+  PoolMark pm(c);
   double* tmp = c->alloc(k);
   launch_deriv_contract(Cb, n, r, Cb, 0, r, k, tmp, c->partials, c->s);
-  c->sync();
   c->xfer(h.data(), tmp, k * sizeof(double), hipMemcpyDeviceToHost);
-  c->pool_used -= up(k);
-  (void)dout;
   return h;
 }
 
@@ -340,6 +353,7 @@ struct DotBatch {
       reqs.clear();
       return out;
     }
+    PoolMark pm(c);
     double* tmp = c->alloc(total);
     int off = 0;
     for (const Req& q : reqs) {
@@ -356,7 +370,6 @@ struct DotBatch {
     }
     std::vector<double> h(total);
     c->xfer(h.data(), tmp, total * sizeof(double), hipMemcpyDeviceToHost);
-    c->pool_used -= up(total);
     off = 0;
     for (size_t i = 0; i < reqs.size(); ++i) {
       const int k = reqs[i].k < 0 ? 1 : reqs[i].k;
@@ -441,7 +454,7 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
   const int nwork = nroots + nbuf;
   const int nkeep = std::min(maxsub / 2, 2 * nwork);
   const double pfloor = 0.05;
-  int64_t mark = c->pool_used;
+  PoolMark pm(c);
   std::vector<double*> V(maxsub), W(maxsub);
   double* Vb = c->alloc((int64_t)maxsub * nvt);
   double* Wb = c->alloc((int64_t)maxsub * nvt);
@@ -570,6 +583,50 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
         conv[k] = rn < tol && !cplx_k[k];
       }
     }
+    // A wanted root that is one of a complex-conjugate Ritz pair: its
+    // residual is that of the complex vector x = V(yr + i yi) with
+    // theta = a + ib, i.e. W yr - a V yr + b V yi and W yi - b V yr - a V yi.
+    // Converged, the excited-state energy is complex: an error, not a root.
+    for (int k = 0; k < std::min(nroots, std::min(nr_now, nx)); ++k) {
+      if (!cplx_k[k]) continue;
+      const int col = ord[k];
+      PoolMark pk(c);
+      double* rr = c->alloc(nvt);
+      double* ri = c->alloc(nvt);
+      std::vector<double> yr(nv), yi(nv);
+      double yn = 0;
+      for (int j = 0; j < nv; ++j) {
+        yr[j] = Y[j * nv + col].real();
+        yi[j] = Y[j * nv + col].imag();
+        yn += yr[j] * yr[j] + yi[j] * yi[j];
+      }
+      yn = std::sqrt(yn);
+      for (int j = 0; j < nv; ++j) {
+        yr[j] /= yn;
+        yi[j] /= yn;
+      }
+      const double a = w[col].real(), b = w[col].imag();
+      std::vector<double> cr(nv), ci(nv);
+      for (int j = 0; j < nv; ++j) {
+        cr[j] = -a * yr[j] + b * yi[j];  // V part of the real residual
+        ci[j] = -b * yr[j] - a * yi[j];  // V part of the imaginary residual
+      }
+      c->fill(rr, nvt, 0.0);
+      c->fill(ri, nvt, 0.0);
+      multi_axpy(c, Wb, nv, nvt, yr, rr);
+      multi_axpy(c, Vb, nv, nvt, cr, rr);
+      multi_axpy(c, Wb, nv, nvt, yi, ri);
+      multi_axpy(c, Vb, nv, nvt, ci, ri);
+      DotBatch dbc;
+      const int i1 = dbc.dot(rr, rr), i2 = dbc.dot(ri, ri);
+      const auto res = dbc.run(c, nvt);
+      const double rn = std::sqrt(res[i1][0] + res[i2][0]);
+      if (rn < tol) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "excited state %d converged to a complex energy %.10f %+.3ei", k, a, b);
+        throw SccError(SCC_ECOMPLEX, msg);
+      }
+    }
     if (c->opt.verbose) {
       c->log("  %s davidson it %3d  nv %2d  max|r| %.3e", left ? "left " : "right", it, nv, maxres);
       for (int k = 0; k < nroots; ++k) c->log("  w%d %.8f%s", k, th[k] - c->E0, conv[k] ? "*" : "");
@@ -580,7 +637,6 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     if (done) {
       evals.assign(th.begin(), th.begin() + nroots);
       for (int k = 0; k < nroots; ++k) c->cp(out[k], Xr[k], nvt);
-      c->pool_used = mark;
       return SCC_OK;
     }
     int nnew = 0;
@@ -615,7 +671,6 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       if (nv < maxsub) add_vector(q);
     }
   }
-  c->pool_used = mark;
   c->err = "Davidson iterations did not converge";
   return SCC_ENOCONV;
 }
@@ -647,7 +702,7 @@ int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& ite
       gr.push_back(c->R[k]);
       gl.push_back(c->Lv[k]);
     }
-  int64_t mark = c->pool_used;
+  PoolMark pm(c);
   std::vector<double*> outR(ns), outL(ns);
   for (int k = 0; k < ns; ++k) {
     outR[k] = c->alloc(nst);
@@ -707,7 +762,6 @@ int excited_at_fixed_zeta(scc_ctx* c, double tol, int maxit, bool warm, int& ite
     c->cp(c->R[k], outR[k], nst);
     if (need_left) c->cp(c->Lv[k], outL[k], nst);
   }
-  c->pool_used = mark;
   (void)nvt;
   return SCC_OK;
 }
@@ -750,7 +804,7 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
   }
   if (use_scc) {
     const int64_t nst = c->sz.nst;
-    int64_t mark = c->pool_used;
+    PoolMark pm(c);
     std::vector<double*> prev(ns);
     for (int k = 0; k < ns; ++k) prev[k] = c->alloc(nst);
     std::vector<double>& Jz = c->Jz;
@@ -770,11 +824,11 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
       std::vector<double> O = pair_overlaps(c);
       double dR = 0, omax = 0;
       for (int k = 0; k < ns; ++k) {
+        PoolMark pk(c);
         double* dif = c->alloc(nst);
         c->cp(dif, c->R[k], nst);
         c->axpby(-1.0, prev[k], 1.0, dif, nst);
         dR = std::max(dR, std::sqrt(c->dot(dif, dif, nst)));
-        c->pool_used -= up(nst);
       }
       for (double x : O) omax = std::max(omax, std::fabs(x));
       c->log(" scc it %2d  max|O| %.3e  |dR| %.3e  zeta0 %.8f  (inner tol %.1e)\n", it, omax, dR, z[0], tol_it);
@@ -787,6 +841,7 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
         // finite-difference Jacobian dO/dzeta with the X3 states held fixed
         Jz.assign(np * np, 0.0);
         const double h = 1e-4;
+        PoolMark pk(c);
         std::vector<double*> keepR(ns), keepL(ns);
         for (int k = 0; k < ns; ++k) {
           keepR[k] = c->alloc(nst);
@@ -810,7 +865,6 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
             c->cp(c->Lv[k], keepL[k], nst);
           }
         }
-        c->pool_used -= 2 * ns * up(nst);
       } else if (!Oprev.empty()) {
         // Broyden update of the Jacobian
         std::vector<double> dz(np), dO(np);
@@ -833,7 +887,6 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
       zprev = z;
       for (int p = 0; p < np; ++p) z[p] -= step[p];
     }
-    c->pool_used = mark;
     c->zeta = z;
     if (!conv) {
       c->err = "SCC iterations did not converge";
@@ -856,7 +909,7 @@ int excited_solve(scc_ctx* c, scc_info* info) {
   const double tol = c->opt.tol_residual, tov = c->opt.tol_overlap;
   int iters = 0, rc;
   if (c->opt.precision == 1) {
-    c->ex->set_lowp(true);
+    c->set_lowp(true);
     try {
       rc = excited_pass(c, std::max(tol, LOWP_TOL), std::max(tov, LOWP_TOL), false, iters);
     } catch (const SccError& e) {
@@ -878,93 +931,7 @@ int excited_solve(scc_ctx* c, scc_info* info) {
   return SCC_OK;
 }
 
-// ---------------------------------------------------------------------------
-// GMRES (right-preconditioned, restarted)
-// ---------------------------------------------------------------------------
 using LinOp = std::function<void(const double*, double*)>;
-
-int gmres(scc_ctx* c, int64_t n, const LinOp& A, const LinOp& Minv, const double* b, double* x, double tol,
-          int maxit, int& iters, double& relres) {
-  int64_t mark = c->pool_used;
-  std::vector<double*> V(GMRES_M + 1), Z(GMRES_M);
-  for (int i = 0; i <= GMRES_M; ++i) V[i] = c->alloc(n);
-  for (int i = 0; i < GMRES_M; ++i) Z[i] = c->alloc(n);
-  double* w = c->alloc(n);
-  double bn = std::sqrt(c->dot(b, b, n));
-  if (bn == 0) {
-    c->fill(x, n, 0.0);
-    c->pool_used = mark;
-    relres = 0;
-    return SCC_OK;
-  }
-  iters = 0;
-  for (int outer = 0; outer < maxit; ++outer) {
-    // r = b - A x
-    A(x, w);
-    c->cp(V[0], b, n);
-    c->axpby(-1.0, w, 1.0, V[0], n);
-    double beta = std::sqrt(c->dot(V[0], V[0], n));
-    relres = beta / bn;
-    c->log("  gmres restart %d  rel. residual %.3e\n", outer, relres);
-    if (relres < tol) {
-      c->pool_used = mark;
-      return SCC_OK;
-    }
-    c->axpby(0.0, V[0], 1.0 / beta, V[0], n);
-    std::vector<double> H((GMRES_M + 1) * GMRES_M, 0.0), cs(GMRES_M), sn(GMRES_M), gv(GMRES_M + 1, 0.0);
-    gv[0] = beta;
-    int j = 0;
-    for (; j < GMRES_M; ++j) {
-      ++iters;
-      Minv(V[j], Z[j]);
-      A(Z[j], w);
-      for (int i = 0; i <= j; ++i) {
-        double h = c->dot(V[i], w, n);
-        H[i * GMRES_M + j] = h;
-        c->axpby(-h, V[i], 1.0, w, n);
-      }
-      // second Gram-Schmidt pass for stability
-      for (int i = 0; i <= j; ++i) {
-        double h = c->dot(V[i], w, n);
-        H[i * GMRES_M + j] += h;
-        c->axpby(-h, V[i], 1.0, w, n);
-      }
-      double hn = std::sqrt(c->dot(w, w, n));
-      H[(j + 1) * GMRES_M + j] = hn;
-      if (hn > 0) {
-        c->cp(V[j + 1], w, n);
-        c->axpby(0.0, w, 1.0 / hn, V[j + 1], n);
-      }
-      for (int i = 0; i < j; ++i) {
-        double a = H[i * GMRES_M + j], bb = H[(i + 1) * GMRES_M + j];
-        H[i * GMRES_M + j] = cs[i] * a + sn[i] * bb;
-        H[(i + 1) * GMRES_M + j] = -sn[i] * a + cs[i] * bb;
-      }
-      double a = H[j * GMRES_M + j], bb = H[(j + 1) * GMRES_M + j];
-      double r = std::sqrt(a * a + bb * bb);
-      cs[j] = r == 0 ? 1.0 : a / r;
-      sn[j] = r == 0 ? 0.0 : bb / r;
-      H[j * GMRES_M + j] = r;
-      H[(j + 1) * GMRES_M + j] = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
-      if (std::fabs(gv[j + 1]) / bn < 0.3 * tol || hn == 0) {
-        ++j;
-        break;
-      }
-    }
-    int k = std::min(j, GMRES_M);
-    std::vector<double> y(k);
-    for (int i = k - 1; i >= 0; --i) {
-      double s = gv[i];
-      for (int l = i + 1; l < k; ++l) s -= H[i * GMRES_M + l] * y[l];
-      y[i] = s / H[i * GMRES_M + i];
-    }
-    for (int i = 0; i < k; ++i) c->axpby(y[i], Z[i], 1.0, x, n);
-  }
-  c->pool_used = mark;
-  return SCC_ENOCONV;
-}
 
 // ---------------------------------------------------------------------------
 // GCR with recycling: pairs (u_i, c_i = A u_i), c_i orthonormal, kept across
@@ -974,7 +941,7 @@ int gmres(scc_ctx* c, int64_t n, const LinOp& A, const LinOp& Minv, const double
 int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const double* b, double* x, double tol,
         int maxit, int& iters, double& relres, bool warm = false) {
   const int64_t n = rc.n;
-  int64_t mark = c->pool_used;
+  PoolMark pm(c);
   double* r = c->alloc(n);
   double* z = c->alloc(n);
   double* w = c->alloc(n);
@@ -991,7 +958,6 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
   iters = 0;
   relres = 1.0;
   if (bn == 0) {
-    c->pool_used = mark;
     relres = 0;
     return SCC_OK;
   }
@@ -1015,7 +981,6 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
       c->log("  gcr it %3d  true rel. residual %.3e\n", it, tr);
       if (tr < 10 * tol || ++checks > 3) {
         relres = tr;
-        c->pool_used = mark;
         if (tr < 10 * tol) return SCC_OK;
         c->err = "Krylov solve: true residual stays above the tolerance";
         return SCC_ENOCONV;
@@ -1085,7 +1050,6 @@ int gcr(scc_ctx* c, Recycler& rc, const LinOp& A, const LinOp& Minv, const doubl
     c->axpby(al, un, 1.0, x, n);
     c->axpby(-al, cn, 1.0, r, n);
   }
-  c->pool_used = mark;
   if (relres < tol) return SCC_OK;
   c->err = "Krylov solve: iteration limit or space capacity reached";
   return SCC_ENOCONV;
@@ -1123,14 +1087,16 @@ void set_lagrangian_point(scc_ctx* c) {
   Model& m = c->m;
   const int64_t nov = c->sz.nov;
   const int ns = m.d.ns;
-  double* tmp = c->alloc(c->sz.nvt);
-  c->get(m.t1, tmp);
-  c->get(m.t2, tmp + nov);
-  c->put(m.pt1, tmp);
-  c->put(m.pt2, tmp + nov);
-  c->put(m.nac_t1c, tmp);
-  c->put(m.nac_t2c, tmp + nov);
-  c->pool_used -= up(c->sz.nvt);
+  {
+    PoolMark pm(c);
+    double* tmp = c->alloc(c->sz.nvt);
+    c->get(m.t1, tmp);
+    c->get(m.t2, tmp + nov);
+    c->put(m.pt1, tmp);
+    c->put(m.pt2, tmp + nov);
+    c->put(m.nac_t1c, tmp);
+    c->put(m.nac_t2c, tmp + nov);
+  }
   for (int p = 0; p < m.d.npairs(); ++p) c->set_scalar(m.pz[p], c->zeta[p]);
   for (int k = 0; k < ns; ++k) {
     c->put_state(m.pr[k], c->R[k]);
@@ -1251,7 +1217,7 @@ int orbital_response(scc_ctx* c, const std::vector<Seg>& segs, const std::vector
     else
       c->fill(c->tp(segs[i].mult), segs[i].n, 0.0);
   }
-  int64_t mark = c->pool_used;
+  PoolMark pm(c);
   c->fill(c->tp(m.mF), nov, 0.0);
   c->run(m.p_kappa);
   double* rhs = c->alloc(nov);
@@ -1283,7 +1249,6 @@ int orbital_response(scc_ctx* c, const std::vector<Seg>& segs, const std::vector
   int rc = gcr(c, c->rec_k, applyF, precF, rhs, c->kbar, c->opt.tol_residual, std::max(c->opt.max_iter, c->rec_k.cap),
                itk, relk);
   c->put(m.mF, c->kbar);
-  c->pool_used = mark;
   if (rc) return rc;
   c->have_mult = true;
   c->mult_kind = kind;
@@ -1297,7 +1262,7 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   const int64_t n = c->sz.nlag;
   set_lagrangian_point(c);
   auto segs = lag_segments(c);
-  int64_t mark = c->pool_used;
+  PoolMark pm(c);
   double* b = c->alloc(n);
   double* x = c->alloc(n);
   c->fill(x, n, 0.0);
@@ -1336,14 +1301,10 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   // away from its true residual (directions of large norm amplify the
   // product rounding), so a reduced-precision pass is no usable start.
   rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, iters, rel);
-  if (rc) {
-    c->pool_used = mark;
-    return rc;
-  }
+  if (rc) return rc;
   int itk = 0;
   double relk = 0;
   rc = orbital_response(c, segs, offs, x, kind, mm, nn, itk, relk);
-  c->pool_used = mark;
   if (rc) return rc;
   if (info) {
     info->iterations = iters + itk;
@@ -1406,6 +1367,7 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
       off += sg.n;
     }
   }
+  PoolMark pm(c);
   LagPrec lp = lag_prec_setup(c);
   auto prec = [&](const double* in, double* out) { lag_prec(c, lp, segs, offs, in, out); };
   // out_j = J^T in_j for the listed slots (at most nbt), other slots zero
@@ -1625,6 +1587,7 @@ int guarded(scc_ctx* c, scc_info* info, F&& f) {
   auto t0 = std::chrono::steady_clock::now();
   double f0 = c ? c->flops : 0;
   int rc;
+  if (c) c->used_lowp = false;
   try {
     if (c) {
       // order after the caller's stream
@@ -1643,11 +1606,23 @@ int guarded(scc_ctx* c, scc_info* info, F&& f) {
     if (c) c->err = e.what();
     rc = SCC_EDEVICE;
   }
-  // every call leaves the executor in FP64 mode
-  if (c) c->ex->set_lowp(false);
+  // every call leaves the executor in FP64 mode and the solver pool as it
+  // found it; a call that did not release its pool use is an internal error
+  if (c) {
+    c->ex->set_lowp(false);
+    if (c->pool_used != c->pool_base) {
+      if (rc == SCC_OK) {
+        c->err = "internal error: solver pool not released (" + std::to_string(c->pool_used - c->pool_base) +
+                 " doubles)";
+        rc = SCC_EDEVICE;
+      }
+      c->pool_used = c->pool_base;
+    }
+  }
   if (info) {
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->flops_mfma = c ? c->flops - f0 : 0;
+    info->precision = c && c->used_lowp ? 1 : 0;
     if (rc) info->converged = 0;
   }
   return rc;
@@ -1757,6 +1732,7 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     c->rec_k.cap = c->sz.cap_k;
     c->rec_k.U = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
     c->rec_k.C = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
+    c->pool_base = c->pool_used;
     // constants
     Model& m = c->m;
     std::vector<double> In((size_t)dd.n * dd.n, 0.0), Io((size_t)dd.o * dd.o, 0.0);
@@ -1822,10 +1798,15 @@ int scc_set_hamiltonian_fixed_basis(scc_ctx* c, const double* h, const double* c
     }
     C = ref;
     // Roothaan iterations: F(C) diagonalised, occupied = lowest o orbitals,
-    // until the Fock matrix commutes with the density, max |F D - D F| < tol
+    // until the Fock matrix commutes with the density, max |F D - D F| < tol.
+    // The matrix diagonalised is Pulay's DIIS extrapolation of the last
+    // eight Fock matrices (error vectors F D - D F): plain Roothaan steps
+    // oscillate with growing amplitude for some systems.
     const double tol = std::min(1e-12, 1e-2 * c->opt.tol_residual);
     int it = 0;
     double comm = 1.0;
+    const int ndiis = 8;
+    std::vector<std::vector<double>> Fh, Eh;
     for (; it < 500; ++it) {
       c->xfer(c->tp(m.Cmo), C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice);
       c->run(m.p_aofock);
@@ -1839,14 +1820,56 @@ int scc_set_hamiltonian_fixed_basis(scc_ctx* c, const double* h, const double* c
           D[(size_t)p * N + q] = x;
         }
       comm = 0;
+      std::vector<double> err((size_t)N * N);
       for (int p = 0; p < N; ++p)
         for (int q = 0; q < N; ++q) {
           double x = 0;
           for (int r = 0; r < N; ++r) x += F[(size_t)p * N + r] * D[(size_t)r * N + q] - D[(size_t)p * N + r] * F[(size_t)r * N + q];
+          err[(size_t)p * N + q] = x;
           comm = std::max(comm, std::fabs(x));
         }
-      if (comm < tol) break;
-      eig_sym(N, F, w, V);
+      const bool done = comm < tol;
+      if (done) {
+        // canonical orbitals of the converged Fock matrix (a rotation within
+        // the occupied and within the virtual blocks; D is unchanged)
+        eig_sym(N, F, w, V);
+        for (int k = 0; k < N; ++k) {
+          double sgn = 0;
+          for (int p = 0; p < N; ++p) sgn += ref[(size_t)p * N + k] * V[(size_t)p * N + k];
+          if (sgn < 0)
+            for (int p = 0; p < N; ++p) V[(size_t)p * N + k] = -V[(size_t)p * N + k];
+        }
+        C = V;
+        break;
+      }
+      Fh.push_back(F);
+      Eh.push_back(err);
+      if ((int)Fh.size() > ndiis) {
+        Fh.erase(Fh.begin());
+        Eh.erase(Eh.begin());
+      }
+      const int nh = (int)Fh.size(), n1 = nh + 1;
+      std::vector<double> B((size_t)n1 * n1, -1.0), cf(n1, 0.0);
+      B[(size_t)nh * n1 + nh] = 0.0;
+      double bscale = 0;
+      for (int i = 0; i < nh; ++i)
+        for (int j = 0; j <= i; ++j) {
+          double x = 0;
+          for (size_t e = 0; e < err.size(); ++e) x += Eh[i][e] * Eh[j][e];
+          B[(size_t)i * n1 + j] = B[(size_t)j * n1 + i] = x;
+          if (i == j) bscale = std::max(bscale, x);
+        }
+      if (bscale > 0)
+        for (int i = 0; i < nh; ++i)
+          for (int j = 0; j < nh; ++j) B[(size_t)i * n1 + j] /= bscale;
+      cf[nh] = -1.0;
+      std::vector<double> Fx = F;
+      if (solve_linear(n1, B, cf)) {
+        std::fill(Fx.begin(), Fx.end(), 0.0);
+        for (int i = 0; i < nh; ++i)
+          for (size_t e = 0; e < Fx.size(); ++e) Fx[e] += cf[i] * Fh[i][e];
+      }
+      eig_sym(N, Fx, w, V);
       // phase: each orbital overlaps its reference orbital positively
       for (int k = 0; k < N; ++k) {
         double sgn = 0;
@@ -1948,7 +1971,7 @@ int scc_ground(scc_ctx* c, const double* guess_t, double* e0, scc_info* info) {
       // the residual judges the guess: it is used only if its residual is
       // below that of the plain start (the MP2 amplitudes, the first step
       // from t = 0)
-      int64_t mark = c->pool_used;
+      PoolMark pm(c);
       double* r = c->alloc(nvt);
       double* tm = c->alloc(nvt);
       auto resnorm = [&](const double* t) {
@@ -1973,7 +1996,6 @@ int scc_ground(scc_ctx* c, const double* guess_t, double* e0, scc_info* info) {
         c->put(m.t2, tm + nov);
         if (info) info->fallback_used = 1;
       }
-      c->pool_used = mark;
     }
     double rn = 0;
     int rc = ground_solve(c, c->opt.tol_residual, c->opt.max_iter, rn);
@@ -2062,10 +2084,22 @@ int scc_multipliers(scc_ctx* c, int kind, int m, int n, scc_info* info) {
   return guarded(c, info, [&]() -> int { return multipliers_solve(c, kind, m, n, info); });
 }
 
-int scc_densities(scc_ctx* c, double* d1, double* z3, double* kappa_bar) {
+int scc_densities(scc_ctx* c, int kind, int mm, int nn, double* d1, double* z3, double* kappa_bar) {
   if (!c) return SCC_EINVAL;
-  if (!c->have_mult) return SCC_ESTATE;
+  const int ns = c->m.d.ns;
+  if (kind < 0 || kind > 1 || nn < 0 || nn >= ns || (kind == 1 && (mm < 0 || mm >= ns || mm == nn))) {
+    c->err = "bad target";
+    return SCC_EINVAL;
+  }
+  if (!c->have_excited) {
+    c->err = "scc_densities before scc_excited";
+    return SCC_ESTATE;
+  }
   return guarded(c, nullptr, [&]() -> int {
+    if (!(c->have_mult && c->mult_kind == kind && c->mult_n == nn && (kind == 0 || c->mult_m == mm))) {
+      int rc = multipliers_solve(c, kind, mm, nn, nullptr);
+      if (rc) return rc;
+    }
     integral_adjoints(c);
     if (c->fixed_basis) {
       c->run(c->m.p_aodens);
@@ -2242,7 +2276,7 @@ int scc_eval_residual(scc_ctx* c, const double* t, const double* zeta, const dou
         c->fill(c->tp(m.xs[k].r2), nov * nov, 0.0);
       }
     }
-    c->ex->set_lowp(c->opt.precision == 1);
+    c->set_lowp(c->opt.precision == 1);
     c->run(m.p_res);
     c->ex->set_lowp(false);
     c->get(m.res.E, out);

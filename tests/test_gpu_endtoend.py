@@ -99,17 +99,27 @@ def test_two_electron_exact():
     ctx, e0, E, z, grads, nacs = _run_gpu(S)
     assert abs(e0 - w[0]) < E_TOL
     assert np.abs(np.asarray(E) - w[1:1 + S.nstates]).max() < E_TOL
+    # phase-match each FCI vector to the library's state exp(T)(R0 + R1 + R2)|HF>
+    nov = S.o * S.v
+    tv = ctx.get(0).cpu().numpy()
+    T = fs.expm(fs.cluster_op(tv[:nov].reshape(S.v, S.o), tv[nov:].reshape(S.v, S.o, S.v, S.o)))
+    vecs = []
+    for k in range(S.nstates):
+        r = ctx.get(1, k).cpu().numpy()
+        psi = T @ fs.vector(float(r[0]), r[1:1 + nov].reshape(S.v, S.o), r[1 + nov:].reshape(S.v, S.o, S.v, S.o))
+        u = U[:, 1 + k] * np.sign(U[:, 1 + k] @ psi)
+        assert abs(abs(u @ psi) - 1.0) < 1e-9     # O_kk = 1 is the FCI norm for two electrons
+        vecs.append(u)
     for c in range(S.ncoord):
         g1 = np.einsum("Jpq,Jrs->pqrs", S.dL[c], L) + np.einsum("Jpq,Jrs->pqrs", L, S.dL[c])
         H1 = fs.hamiltonian(S.dh[c], g1)
         for k in range(S.nstates):
-            ref = U[:, 1 + k] @ H1 @ U[:, 1 + k]
+            ref = vecs[k] @ H1 @ vecs[k]
             assert abs(grads[k][c] - ref) < G_TOL
         for (m, n) in S.nacs:
-            ref = U[:, 1 + m] @ H1 @ U[:, 1 + n] / (w[1 + n] - w[1 + m])
-            # the FCI vectors carry arbitrary signs: compare magnitudes, and
-            # the exact antisymmetry of the couplings
-            assert abs(abs(nacs[(m, n)][c]) - abs(ref)) < G_TOL
+            for a, b in [(m, n), (n, m)]:
+                ref = vecs[a] @ H1 @ vecs[b] / (w[1 + b] - w[1 + a])
+                assert abs(nacs[(a, b)][c] - ref) < G_TOL
             assert abs(nacs[(m, n)][c] + nacs[(n, m)][c]) < G_TOL
 
 
@@ -228,7 +238,7 @@ def test_fixed_basis_displaced_geometry():
             print(f"  nac {(a, b)} max err {err:.2e}", flush=True)
             assert err < G_TOL
     # densities come back in the fixed basis
-    d1, z3, kb = ctx.densities()
+    d1, z3, kb = ctx.densities(1, S.nacs[0][1], S.nacs[0][0])
     d1_ref = ref[("nac", S.nacs[0][1], S.nacs[0][0])]["D1"]
     assert np.abs(d1.cpu().numpy() - d1_ref).max() < 1e-9 * max(1.0, np.abs(d1_ref).max())
 
@@ -278,3 +288,95 @@ def test_batched_targets_match_single_target_solves():
         assert np.abs(g[k] - grads[k]).max() < 1e-9
     for i, p in enumerate(pairs):
         assert np.abs(d[i] - nacs[p]).max() < 1e-9
+
+
+def test_consecutive_geometries_on_one_context():
+    """Three displaced geometries solved one after another on one context
+    (gradients and couplings of every target in lockstep) give the results of
+    a fresh context per geometry: no state leaks from one geometry into the
+    next, and every call releases the solver memory it used (a call that did
+    not is reported as an error by the library)."""
+    from paper_2403_01007_amd import Context
+    from synth_inputs import family_geometries
+    S = make_system("o5v19", seed=7)
+    print("[three geometries on one context o5v19]", flush=True)
+    pairs = list(S.nacs) + [(n, m) for (m, n) in S.nacs]
+    states = list(range(S.nstates))
+
+    def solve(ctx, x):
+        h, L = S.at(x)
+        ctx.set_hamiltonian_fixed_basis(h, L)
+        E, z, _ = ctx.excited()
+        g, d, _ = ctx.gradients_and_couplings(states, pairs, S.dh, S.dL)
+        return E, z, g, d
+
+    shared = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
+    for i, x in enumerate(family_geometries(S.ncoord, range(20000, 20003))):
+        a = solve(shared, x)
+        fresh = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
+        b = solve(fresh, x)
+        fresh.close()
+        print(f"  geometry {i}: E {a[0]}", flush=True)
+        assert np.abs(a[0] - b[0]).max() < E_TOL
+        assert np.abs(a[1] - b[1]).max() < 1e-9
+        assert np.abs(a[2] - b[2]).max() < G_TOL
+        assert np.abs(a[3] - b[3]).max() < G_TOL
+
+
+def test_failure_paths():
+    """Error semantics of the boundary, forced from the host: an iteration
+    limit (SCC_ENOCONV), a workspace below the required size (SCC_ENOMEM),
+    and guesses that are not finite (rejected by their residual, with the
+    plain start used instead)."""
+    import ctypes
+
+    import torch
+    from paper_2403_01007_amd import Context, binding
+    from paper_2403_01007_amd.binding import SccError
+    S = make_system("o2v4")
+    print("[failure paths o2v4]", flush=True)
+    h, L = S.at(np.zeros(S.ncoord))
+    # iteration limit
+    ctx = Context(S.o, S.v, S.nj, S.nstates, max_iter=2)
+    ctx.set_hamiltonian(h, L)
+    with pytest.raises(SccError) as e:
+        ctx.ground()
+    assert e.value.code == -3
+    with pytest.raises(SccError) as e:
+        ctx.excited()
+    assert e.value.code == -3
+    ctx.close()
+    # workspace one byte short of the required size
+    lib = binding.load_library()
+    dims = binding.Dims(S.o, S.v, S.nj, S.nstates)
+    opts = binding.Options(1e-10, 1e-11, 200, 1, 0, 0, 0)
+    need = binding.workspace_bytes(S.o, S.v, S.nj, S.nstates, opts)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda:0")
+    base = (ws.data_ptr() + 255) // 256 * 256
+    handle = ctypes.c_void_p()
+    rc = lib.scc_create(ctypes.byref(dims), ctypes.byref(opts), ctypes.c_void_p(base), need - 1, None,
+                        ctypes.byref(handle))
+    assert rc == -7 and not handle.value
+    # non-finite guesses: the plain start is used and the solution is unchanged
+    ref = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
+    ref.set_hamiltonian(h, L)
+    e_ref, _ = ref.ground()
+    E_ref, z_ref, _ = ref.excited()
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
+    ctx.set_hamiltonian(h, L)
+    nov = S.o * S.v
+    bad_t = np.full(nov + nov * nov, np.nan)
+    e0, info = ctx.ground(bad_t)
+    assert info.fallback_used == 1 and info.converged == 1
+    assert abs(e0 - e_ref) < E_TOL
+    nst = 1 + nov + nov * nov
+    npair = S.nstates * (S.nstates - 1) // 2
+    bad_r = np.full(S.nstates * nst + npair, np.nan)
+    E, z, info = ctx.excited(bad_r)
+    assert info.fallback_used == 1 and info.converged == 1
+    assert np.abs(E - E_ref).max() < E_TOL
+    assert np.abs(z - z_ref).max() < 1e-9
+    # a bad target and a bad coordinate count are rejected before any work
+    with pytest.raises(SccError) as e:
+        ctx.densities(1, 0, 0)
+    assert e.value.code == -1
