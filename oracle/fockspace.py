@@ -194,16 +194,11 @@ def singlet_fci(fs: FockSpace, H, nroots):
 
 
 def spin_squared(fs: FockSpace):
-    """S^2 = S_- S_+ + S_z + S_z^2 on the Ms = 0 space via the singlet trick:
-    for closed-shell Ms = 0 spaces, S^2 = sum_pq (E_pq E_qp) cross terms;
-    we use S^2 = -sum_pq e_pq e_qp + N(4 - N... ) identity written directly
-    through alpha/beta parts, built from E_pq and the number operator."""
-    # S^2 = 1/2 sum_pq E_pq E_qp ... derived form: S^2 = N - 1/4 N^2 - 1/2 sum_pq E_pq E_qp
-    # + (number of doubly occupied terms) is awkward; use the exact relation
-    # sum_pq E_pq E_qp = N(n+2) - N^2/2 - 2 S^2 for N electrons in n orbitals.
+    """S^2 on the Ms = 0 space from the singlet excitation operators:
+    for Ne electrons in n spatial orbitals,
+        sum_pq E_pq E_qp = Ne (n + 2) - Ne^2 / 2 - 2 S^2,
+    so S^2 = (Ne (n + 2) - Ne^2 / 2) / 2 - (1/2) sum_pq E_pq E_qp."""
     n = fs.n
     Ne = 2 * fs.o
-    Er = fs.E.reshape(n * n, fs.dim, fs.dim)
     EEt = np.einsum("pqIK,qpKJ->IJ", fs.E, fs.E)
-    del Er
     return 0.5 * (Ne * (n + 2) - 0.5 * Ne * Ne) * np.eye(fs.dim) - 0.5 * EEt

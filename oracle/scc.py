@@ -6,7 +6,10 @@ Steps, in the paper's order:
   1. RHF in the fixed orthonormal basis, MO integrals (orbital-explicit
      Hbar section: kappa = 0 are the HF orbitals at the geometry);
   2. ground state Omega(t) = 0 (CC theory section);
-  3. EOM right/left eigenvectors of the full matrix calHbar (EOM section);
+  3. EOM right/left eigenvectors of calHbar (EOM section): from the dense
+     matrix for small systems, else by a plain nonsymmetric Davidson
+     iteration on the excited-excited block with the reference row and
+     column from the block structure (R0 = eta.R / omega, L0 = 0);
   4. SCC: zeta_kl with O_kl = <psi_k|P|psi_l> = 0, solved together with the
      ground and excited states (SCC theory section; natural projection);
   5. Lagrangian of the gradient / coupling: the multipliers solve the
@@ -82,20 +85,35 @@ class Packer:
 # RHF in the fixed basis
 # ---------------------------------------------------------------------------
 def rhf(h, L, o, C0=None, tol=1e-13, maxiter=500):
-    """Roothaan iterations (no extrapolation: the displaced geometries start
-    from nearby orbitals); returns canonical MO coefficients whose columns
-    are phase-aligned with C0 (default identity)."""
+    """Roothaan iterations with Pulay's DIIS extrapolation of the Fock matrix
+    (error vectors F D - D F, orthonormal basis, last 8 iterations); returns
+    canonical MO coefficients whose columns are phase-aligned with C0
+    (default identity).  Plain Roothaan steps oscillate for some of the
+    synthetic systems; the converged orbitals are the same."""
     n = h.shape[0]
     C = np.eye(n) if C0 is None else C0.copy()
+    Fs, Es = [], []
     for it in range(maxiter):
         Co = C[:, :o]
         D = Co @ Co.T
         Jm = np.einsum("Jpq,Jrs,rs->pq", L, L, D)
         K = np.einsum("Jps,Jsq->pq", np.einsum("Jpr,rs->Jps", L, D), L)
         F = h + 2 * Jm - K
-        w, C = np.linalg.eigh(F)
-        if np.abs(F @ D - D @ F).max() < tol:
+        err = F @ D - D @ F
+        if np.abs(err).max() < tol:
+            w, C = np.linalg.eigh(F)
             break
+        Fs, Es = (Fs + [F])[-8:], (Es + [err])[-8:]
+        m = len(Fs)
+        B = -np.ones((m + 1, m + 1))
+        B[m, m] = 0.0
+        for i in range(m):
+            for j in range(m):
+                B[i, j] = np.sum(Es[i] * Es[j])
+        rhs = np.zeros(m + 1)
+        rhs[m] = -1.0
+        c = np.linalg.lstsq(B, rhs, rcond=None)[0][:m]
+        w, C = np.linalg.eigh(sum(ci * Fi for ci, Fi in zip(c, Fs)))
     else:
         raise RuntimeError("RHF did not converge")
     ref = np.eye(n) if C0 is None else C0
@@ -229,13 +247,173 @@ def packed_from_state(P, st):
     return torch.cat([torch.as_tensor(st[0], dtype=f64).reshape(1), P.pack(st[1], st[2])])
 
 
-def eom_states(h, g, o, t1, t2, nstates, zeta=None, rstates=None, prev=None):
+DENSE_EOM_LIMIT = 3000   # packed amplitudes above which the EOM states come from Davidson
+
+
+def davidson(apply, diag, nroots, guesses, tol, maxit=400, maxsub=None, nbuf=2):
+    """Plain nonsymmetric Davidson iteration for the eigenvalues of lowest
+    real part of the linear map `apply`: orthonormal search space V, images
+    W = A V, subspace matrix V^T W, preconditioned residuals (diag - theta)^-1 r
+    added after two passes of Gram-Schmidt.  Returns (theta [nwork], X [n,
+    nwork]) with the first nroots converged to ||A x - theta x|| < tol.
+    Complex Ritz pairs contribute their real and imaginary parts to the
+    search space; a wanted root that converges complex is an error."""
+    n = diag.size
+    nwork = nroots + nbuf
+    maxsub = maxsub or max(40, 8 * nwork)
+    V, W = [], []
+
+    def add(vec):
+        n0 = np.linalg.norm(vec)
+        if not n0 > 0:
+            return False
+        vec = vec / n0
+        for _ in range(2):
+            for u in V:
+                vec = vec - (u @ vec) * u
+        nv = np.linalg.norm(vec)
+        if nv < 1e-10:      # (numerically) inside the search space already
+            return False
+        V.append(vec / nv)
+        W.append(apply(V[-1]))
+        return True
+
+    for gv in guesses:
+        add(np.array(gv, dtype=np.float64))
+    for k in np.argsort(diag):
+        if len(V) >= nwork + 1:
+            break
+        e = np.zeros(n)
+        e[k] = 1.0
+        add(e)
+    for it in range(maxit):
+        Vm, Wm = np.array(V).T, np.array(W).T
+        w, Y = np.linalg.eig(Vm.T @ Wm)
+        order = np.argsort(w.real)[:nwork]
+        X, AX, th, cplx, res = [], [], [], [], []
+        for k in order:
+            y = Y[:, k]
+            y = y / np.linalg.norm(y)
+            x, ax = Vm @ y, Wm @ y
+            r = ax - w[k] * x
+            X.append(x)
+            AX.append(ax)
+            th.append(w[k])
+            cplx.append(abs(w[k].imag) > 1e-10 * max(1.0, abs(w[k].real)))
+            res.append(np.linalg.norm(r))
+        for k in range(nroots):
+            if cplx[k] and res[k] < tol:
+                raise RuntimeError("complex excited-state energy")
+        if all(res[k] < tol and not cplx[k] for k in range(nroots)):
+            return np.array([t.real for t in th]), np.array([x.real for x in X]).T
+        new = []
+        for k in range(nwork):
+            if res[k] < tol and not cplx[k]:
+                continue
+            r = AX[k] - th[k] * X[k]
+            den = diag - th[k].real
+            den = np.where(np.abs(den) < 0.05, np.where(den < 0, -0.05, 0.05), den)
+            new.append((r.real / den, r.imag / den if cplx[k] else None))
+        if len(V) + 2 * len(new) > maxsub:
+            # thick restart on the real and imaginary parts of the Ritz vectors
+            keep = [x.real for x in X] + [x.imag for x, c in zip(X, cplx) if c]
+            V, W = [], []
+            for x in keep:
+                add(x)
+        for a, b in new:
+            add(a)
+            if b is not None:
+                add(b)
+    raise RuntimeError("Davidson iterations did not converge")
+
+
+def eom_states_davidson(h, g, o, t1, t2, nstates, eps, zeta=None, rstates=None, prev=None, tol=1e-11):
+    """As eom_states, from Davidson iterations on the excited-excited block of
+    calHbar in packed coordinates (R0 = 0 there): right vectors from the map
+    x -> pack(sigma(unpack(x))), left vectors from its transpose (the
+    reverse-mode derivative of the same map).  R0 = eta.R / omega from the
+    reference row; L0 = 0."""
+    n = h.shape[0]
+    P = Packer(o, n - o)
+    E0 = float(cc.residual(h, g, t1, t2, o, zeta, rstates)[0])
+
+    def right(x):
+        r1, r2 = P.unpack(tt(x))
+        _, s1, s2 = cc.sigma(h, g, t1, t2, o, 0.0, r1, r2, zeta, rstates)
+        return P.pack(s1, s2).numpy()
+
+    def left(y):
+        x = torch.zeros(P.namp, dtype=f64, requires_grad=True)
+        r1, r2 = P.unpack(x)
+        _, s1, s2 = cc.sigma(h, g, t1, t2, o, 0.0, r1, r2, zeta, rstates)
+        (gx,) = torch.autograd.grad(P.pack(s1, s2), x, tt(y))
+        return gx.numpy()
+
+    def eta_dot(x):
+        r1, r2 = P.unpack(tt(x))
+        return float(cc.sigma(h, g, t1, t2, o, 0.0, r1, r2, zeta, rstates)[0])
+
+    diag = E0 + P.denominators(eps)
+    nbuf = 2
+    if prev is None:
+        gr, gl = [], []
+    else:
+        gr = [packed_from_state(P, Rp).numpy()[1:] for (Lp, Rp) in prev]
+        gl = [packed_from_state(P, Lp).numpy()[1:] for (Lp, Rp) in prev]
+    nroots = nstates
+    while True:
+        wr, XR = davidson(right, diag, nroots, gr, tol, nbuf=nbuf)
+        if prev is None:
+            pick = list(range(nstates))
+        else:
+            pick = []
+            for (Lp, Rp) in prev:
+                lp = packed_from_state(P, Lp).numpy()[1:]
+                ov = [abs(lp @ XR[:, k]) / np.linalg.norm(XR[:, k]) for k in range(XR.shape[1])]
+                pick.append(int(np.argmax(ov)))
+        if max(pick) < nroots:      # every picked root is a converged one
+            break
+        nroots = max(pick) + 1
+    # left vectors: the same lowest roots of the transpose, paired by energy
+    wl, XL = davidson(left, diag, nroots, [XR[:, k] for k in range(nroots)] + gl, tol, nbuf=nbuf)
+    Rs, Ls, Es = [], [], []
+    for s_, k in enumerate(pick):
+        Ek = wr[k]
+        re = XR[:, k]
+        rv = np.concatenate([[eta_dot(re) / (Ek - E0)], re])
+        st = state_from_packed(P, tt(rv))
+        rv = rv / np.sqrt(float(cc.overlap(t1, t2, st, st)))
+        if prev is None:
+            r1 = rv[1:1 + P.nov]
+            if r1[np.argmax(np.abs(r1))] < 0:
+                rv = -rv
+        else:
+            lp = packed_from_state(P, prev[s_][0]).numpy()
+            if lp @ rv < 0:
+                rv = -rv
+        kl = int(np.argmin(np.abs(wl[:nroots] - Ek)))
+        if abs(wl[kl] - Ek) > 1e-8 * max(1.0, abs(Ek)):
+            raise RuntimeError("left and right excitation energies differ")
+        lv = np.concatenate([[0.0], XL[:, kl]])
+        lv = lv / (lv @ rv)
+        Rs.append(state_from_packed(P, tt(rv)))
+        Ls.append(state_from_packed(P, tt(lv)))
+        Es.append(Ek)
+    return Rs, Ls, np.array(Es), None
+
+
+def eom_states(h, g, o, t1, t2, nstates, zeta=None, rstates=None, prev=None, method=None, tol=1e-11):
     """Lowest excited right/left eigenvectors, normalised O_kk = 1 and
     calL_k . calR_k = 1; phase: largest |R1| positive (or positive overlap
     with the previous left vector); order: ascending energy (or maximum
-    overlap with the previous states)."""
+    overlap with the previous states).  method: "dense" (eigenvectors of the
+    whole calHbar), "davidson" (eom_states_davidson, residual norm < tol) or
+    None (dense up to DENSE_EOM_LIMIT packed amplitudes)."""
     n = h.shape[0]
     P = Packer(o, n - o)
+    if method == "davidson" or (method is None and P.namp > DENSE_EOM_LIMIT):
+        eps = np.diag(cc.fock(h, g, o).numpy()).copy()
+        return eom_states_davidson(h, g, o, t1, t2, nstates, eps, zeta, rstates, prev, tol=tol)
     M = eom_matrix(h, g, o, t1, t2, zeta, rstates).numpy()
     w, VL, VR = sla.eig(M, left=True, right=True)
     E0 = M[0, 0]
@@ -276,21 +454,33 @@ def eom_states(h, g, o, t1, t2, nstates, zeta=None, rstates=None, prev=None):
 
 
 def scc_solve(h, g, o, eps, nstates, scc=True, tol=1e-12, maxiter=60,
-              start=None):
+              start=None, eom_method=None):
     """Ground + excited states with the orthogonality constraints O_kl = 0
     solved simultaneously; zeta by Newton steps with a finite-difference
-    Jacobian (the root reached from zeta = 0, or continued from `start`)."""
+    Jacobian (the root reached from zeta = 0, or continued from `start`).
+    Iterative EOM vectors (eom_method "davidson", or None above the dense
+    limit) are converged to a residual norm of 1e-11; the SCC loop then
+    stops at |O_kl| below that level and successive right vectors within 10
+    times it (the eigenvector noise of the iteration)."""
     pairs = cc.pair_list(nstates)
     use_scc = scc and o >= 2 and len(pairs) > 0
+    namp = Packer(o, h.shape[0] - o).namp
+    iterative = eom_method == "davidson" or (eom_method is None and namp > DENSE_EOM_LIMIT)
+    tol_eom = 1e-11
+    tol_dr = max(tol, 10 * tol_eom) if iterative else tol
+    tol_o = max(tol, tol_eom) if iterative else tol
+
+    def eom(*a, **k):
+        return eom_states(*a, method=eom_method, tol=tol_eom, **k)
     if start is None:
         t1, t2, E0, _ = solve_ground(h, g, o, eps, tol=tol)
-        R, Lv, E, _ = eom_states(h, g, o, t1, t2, nstates)
+        R, Lv, E, _ = eom(h, g, o, t1, t2, nstates)
         zeta = torch.zeros(len(pairs), dtype=f64)
     else:
         t1, t2, zeta, R, Lv = start.t1, start.t2, start.zeta.clone(), start.R, start.Lv
         t1, t2, E0, _ = solve_ground(h, g, o, eps, t1, t2, zeta if use_scc else None,
                                      R if use_scc else None, tol=tol)
-        R, Lv, E, _ = eom_states(h, g, o, t1, t2, nstates, zeta if use_scc else None,
+        R, Lv, E, _ = eom(h, g, o, t1, t2, nstates, zeta if use_scc else None,
                                  R if use_scc else None, prev=list(zip(Lv, R)))
     it = 0
     if use_scc:
@@ -299,7 +489,7 @@ def scc_solve(h, g, o, eps, nstates, scc=True, tol=1e-12, maxiter=60,
 
         def solve_at(z, Rfix, tstart, prev):
             a, b, e0, _ = solve_ground(h, g, o, eps, tstart[0], tstart[1], z, Rfix, tol=tol)
-            Rn, Ln, En, _ = eom_states(h, g, o, a, b, nstates, z, Rfix, prev=prev)
+            Rn, Ln, En, _ = eom(h, g, o, a, b, nstates, z, Rfix, prev=prev)
             return a, b, e0, Rn, Ln, En
 
         Jz = None
@@ -311,7 +501,7 @@ def scc_solve(h, g, o, eps, nstates, scc=True, tol=1e-12, maxiter=60,
                                      - packed_from_state(Packer(o, h.shape[0] - o), b)).max())
                      for a, b in zip(Rn, R))
             R, Lv, E = Rn, Ln, En
-            if float(torch.abs(Ov).max()) < tol and dR < tol:
+            if float(torch.abs(Ov).max()) < tol_o and dR < tol_dr:
                 break
             if Jz is None:
                 Jz = torch.zeros((len(pairs), len(pairs)), dtype=f64)
@@ -539,7 +729,7 @@ class Lagrangian:
 # ---------------------------------------------------------------------------
 # top-level drivers
 # ---------------------------------------------------------------------------
-def solve_system(system, x=None, nstates=None, scc=True, start=None, C0=None, tol=1e-12):
+def solve_system(system, x=None, nstates=None, scc=True, start=None, C0=None, tol=1e-12, eom_method=None):
     """RHF + SCCSD solution of a synth_inputs.System at coordinates x."""
     o = system.o
     xv = np.zeros(system.ncoord) if x is None else np.asarray(x, dtype=np.float64)
@@ -555,7 +745,7 @@ def solve_system(system, x=None, nstates=None, scc=True, start=None, C0=None, to
     F = cc.fock(h, g, o).numpy()
     eps = np.diag(F).copy()
     ns = system.nstates if nstates is None else nstates
-    sol = scc_solve(h, g, o, eps, ns, scc=scc, start=start, tol=tol)
+    sol = scc_solve(h, g, o, eps, ns, scc=scc, start=start, tol=tol, eom_method=eom_method)
     sol.L = L
     sol.C = C
     return sol

@@ -58,8 +58,10 @@ CONFIGS = {
     # small ragged systems for parity tests (several GEMM tiles + tails)
     "o5v19": dict(o=5, v=19, nj=40, nstates=2, ncoord=3, nacs=[(0, 1)],
                   sf=0.002, sl=0.002),
-    "o6v26": dict(o=6, v=26, nj=70, nstates=3, ncoord=4,
-                  nacs=[(0, 1), (1, 2)], sf=0.002, sl=0.002),
+    # three states with all three pairwise couplings, as in o10v90, at a size
+    # the oracle solves completely
+    "o6v26": dict(o=6, v=26, nj=70, nstates=3, ncoord=6,
+                  nacs=[(0, 1), (0, 2), (1, 2)], sf=0.01, sl=0.01),
     # tiny systems for determinant-space checks
     "o1v5": dict(o=1, v=5, nj=12, nstates=2, ncoord=2, nacs=[(0, 1)],
                  sf=0.01, sl=0.01),

@@ -1,9 +1,13 @@
 """Write oracle reference values for end-to-end parity tests.
 
 Calls only oracle/ and synth_inputs/ (seeded synthetic inputs).  Usage:
-    python tests/golden/make_golden.py o4v12
+    python tests/golden/make_golden.py o4v12            (every coupling in both orders)
+    python tests/golden/make_golden.py o6v26 --one-order
 writes tests/golden/<name>.json with energies, zeta, gradients of every
-state and the requested couplings (both orders) at x = 0.
+state and the requested couplings at x = 0.  It also records the oracle's
+own wall time for the whole geometry and for one of its residual
+evaluations at that size (the ratio is the oracle's cost per geometry in
+units of its own residual, which the benchmark's CPU baseline uses).
 """
 import json
 import os
@@ -16,33 +20,55 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import scc  # noqa: E402
+from oracle import cc, scc  # noqa: E402
 from synth_inputs import make_system  # noqa: E402
 
 
-def main(name):
-    torch.set_num_threads(max(1, len(os.sched_getaffinity(0))))
+def residual_seconds(S):
+    h, L = S.at(np.zeros(S.ncoord))
+    ht, gt = torch.as_tensor(h), cc.chol_to_g(torch.as_tensor(L))
+    t1 = torch.zeros((S.v, S.o), dtype=torch.float64)
+    t2 = torch.zeros((S.v, S.o, S.v, S.o), dtype=torch.float64)
+    cc.residual(ht, gt, t1, t2, S.o)
+    n, t = 0, 0.0
+    while t < 2.0 or n < 3:
+        c0 = time.perf_counter()
+        cc.residual(ht, gt, t1, t2, S.o)
+        t += time.perf_counter() - c0
+        n += 1
+    return t / n
+
+
+def main(name, both_orders=True):
+    threads = max(1, len(os.sched_getaffinity(0)))
+    torch.set_num_threads(threads)
     S = make_system(name)
     t0 = time.time()
     sol = scc.solve_system(S)
-    print(f"solve {time.time() - t0:.1f}s E0 {sol.E0} E {sol.E} zeta {sol.zeta}", flush=True)
+    t_solve = time.time() - t0
+    print(f"solve {t_solve:.1f}s E0 {sol.E0} E {sol.E} zeta {sol.zeta}", flush=True)
     targets = [("grad", k) for k in range(S.nstates)]
     for (m, n) in S.nacs:
-        targets += [("nac", m, n), ("nac", n, m)]
+        targets += [("nac", m, n)] + ([("nac", n, m)] if both_orders else [])
     out = dict(system=name, seed=S.seed, reading=S.reading, o=S.o, v=S.v, nj=S.nj,
                nstates=S.nstates, ncoord=S.ncoord, E0=sol.E0, E=list(map(float, sol.E)),
                zeta=list(map(float, sol.zeta)), grad={}, nac={})
+    t_targets = 0.0
     for tg in targets:
         t1 = time.time()
         r = scc.gradient_and_nacs(S, sol, [tg])[tg]
+        t_targets += time.time() - t1
         print(f"{tg} {time.time() - t1:.1f}s {r['value']}", flush=True)
         if tg[0] == "grad":
             out["grad"][str(tg[1])] = list(map(float, r["value"]))
         else:
             out["nac"][f"{tg[1]},{tg[2]}"] = list(map(float, r["value"]))
+    out["oracle_timing"] = dict(threads=threads, solve_seconds=t_solve, targets_seconds=t_targets,
+                                residual_seconds=residual_seconds(S),
+                                targets=[list(map(str, t)) for t in targets])
     with open(os.path.join(HERE, f"{name}.json"), "w") as f:
         json.dump(out, f, indent=1)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1])
+    main(sys.argv[1], both_orders="--one-order" not in sys.argv[2:])

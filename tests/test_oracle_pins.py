@@ -227,3 +227,57 @@ def test_lagrangian_closed_forms(o2v4_solution):
             om = sol.E[k] - sol.E0
             assert abs(lbar[0] - gam[0] * float(dO) / om) < 1e-10
             off += na + 2
+
+
+def _packed_scale(P):
+    """Packed doubles coordinate of a basis vector E_ai E_bj |HF>: 1 for
+    (ai) < (bj), 2 for (ai) = (bj) (the packed coordinate x stands for
+    1/2 x E_ai E_ai there)."""
+    o, v = P.o, P.v
+    nov = o * v
+    iu0, iu1 = P.iu[0].numpy(), P.iu[1].numpy()
+    return np.concatenate([[1.0], np.ones(nov), np.where(iu0 == iu1, 2.0, 1.0)])
+
+
+@pytest.mark.parametrize("name", ["o2v3", "o2v4"])
+def test_eom_matrix_matches_determinant_space(name):
+    """The oracle's assembled calHbar (reference row and column, the
+    Jacobian of the residual, the E0 diagonal and the {R1, Omega1} doubles
+    term, plus the SCC term with X3) equals the matrix of the projected
+    determinant-space operator P_E exp(-T) H exp(T) P_E, element by element,
+    at random amplitudes with zeta X3 in the cluster operator."""
+    S, h, g = _ham(name)
+    fs = FockSpace(S.n, S.o)
+    H = fs.hamiltonian(h, g)
+    t1, t2 = random_amplitudes(S.o, S.v, seed=5, scale=0.1)
+    ra, rb, _ = _three_states(S.o, S.v)
+    zeta = 0.37
+    x3 = zeta * x3_operator(fs, ra, rb)
+    rs = [tuple(T(x) for x in ra), tuple(T(x) for x in rb)]
+    M = scc.eom_matrix(T(h), T(g), S.o, T(t1), T(t2), T([zeta]), rs).numpy()
+    from oracle.fockspace import hbar
+    Hb = hbar(fs, H, t1, t2, x3)
+    B = fs.basis
+    Mfs = np.linalg.solve(fs.gram, B.T @ Hb @ B)     # columns: coefficients of Hbar |nu>
+    P = scc.Packer(S.o, S.v)
+    d = _packed_scale(P)
+    ref = d[:, None] * Mfs / d[None, :]
+    assert np.abs(M - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name", ["o2v3", "o2v4"])
+def test_davidson_states_match_dense_eigenvectors(name):
+    """The iterative EOM path (Davidson on the excited block, left vectors
+    from the transposed map, R0 from the reference row) reproduces the
+    eigenvectors of the dense calHbar: energies, zeta and normalised right
+    and left vectors of the SCCSD solution."""
+    S = make_system(name)
+    a = scc.solve_system(S, eom_method="dense")
+    b = scc.solve_system(S, eom_method="davidson")
+    assert np.abs(a.E - b.E).max() < 1e-12
+    assert abs(a.E0 - b.E0) < 1e-12
+    assert np.abs((a.zeta - b.zeta).numpy()).max() < 1e-7
+    for k in range(S.nstates):
+        for i in range(3):
+            assert float(torch.abs(torch.as_tensor(a.R[k][i]) - torch.as_tensor(b.R[k][i])).max()) < 1e-10
+            assert float(torch.abs(torch.as_tensor(a.Lv[k][i]) - torch.as_tensor(b.Lv[k][i])).max()) < 1e-10
