@@ -55,6 +55,19 @@ int scc_mlp_workspace_bytes(const scc_mlp_dims* d, int max_batch, size_t* bytes)
 int scc_mlp_forward(const scc_mlp_dims* d, const float* params, int n, const float* X, float* Y, void* workspace,
                     size_t bytes, void* hip_stream);
 
+/* Y [n][nout] = network(X [n][nin]) as scc_mlp_forward (same kernels, same
+ * results), for callers that cannot allocate device memory or pass a
+ * workspace (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  The hidden activations use a library-owned device
+ * array of 4 MiB per device (held until the process ends), so
+ * 2 * n * nhidden must not exceed 1048576 (n <= 2048 at nhidden = 256):
+ * larger n returns -7 before any work.  Allocates nothing.  Every call on a
+ * device shares that device's array: calls that overlap in time on one
+ * device (other streams, other host threads) race and must be serialised
+ * by the caller. */
+int scc_mlp_forward_noalloc(const scc_mlp_dims* d, const float* params, int n, const float* X, float* Y,
+                            void* hip_stream);
+
 /* Loss (device float[1]) and its gradient grad [count] over the batch
  * X [n][nin], targets T [n][nout]. */
 int scc_mlp_loss_grad(const scc_mlp_dims* d, const float* params, int n, const float* X, const float* T, float* loss,

@@ -20,7 +20,8 @@ EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_las
                     "scc_set_hamiltonian", "scc_set_hamiltonian_fixed_basis", "scc_ground", "scc_excited", "scc_multipliers",
                     "scc_densities", "scc_gradient", "scc_nac", "scc_gradients_and_couplings", "scc_get", "scc_eval_residual",
                     "scc_eval_sigma", "scc_eval_left", "scc_profile", "scc_profile_kernels",
-                    "scc_mlp_param_count", "scc_mlp_workspace_bytes", "scc_mlp_forward", "scc_mlp_loss_grad",
+                    "scc_mlp_param_count", "scc_mlp_workspace_bytes", "scc_mlp_forward", "scc_mlp_forward_noalloc",
+                    "scc_mlp_loss_grad",
                     "scc_mlp_train", "scc_pca_workspace_bytes", "scc_pca_fit", "scc_pca_expand"]
 
 
@@ -91,6 +92,7 @@ def load_library():
     lib.scc_mlp_param_count.argtypes = [MD, ctypes.POINTER(ctypes.c_longlong)]
     lib.scc_mlp_workspace_bytes.argtypes = [MD, I, ctypes.POINTER(S)]
     lib.scc_mlp_forward.argtypes = [MD, P, I, P, P, P, S, P]
+    lib.scc_mlp_forward_noalloc.argtypes = [MD, P, I, P, P, P]
     lib.scc_mlp_loss_grad.argtypes = [MD, P, I, P, P, P, P, P, S, P]
     lib.scc_mlp_train.argtypes = [MD, P, P, P, I, P, P, I, I, P, ctypes.c_float, I, P, P, S, P]
     lib.scc_pca_workspace_bytes.argtypes = [I, ctypes.c_longlong, I, ctypes.POINTER(S)]
@@ -343,6 +345,14 @@ class Mlp:
         ws = self._ws(X.shape[0])
         _chk(self.lib.scc_mlp_forward(ctypes.byref(self.d), _ptr(self.params), X.shape[0], _ptr(X), _ptr(Y), _ptr(ws),
                                       ws.numel(), _stream()), "scc_mlp_forward")
+        return Y
+
+    def forward_noalloc(self, X):
+        """As forward, without a workspace (library-owned device scratch)."""
+        X = self._f32(X)
+        Y = self.torch.empty((X.shape[0], self.d.nout), dtype=self.torch.float32, device=self.device)
+        _chk(self.lib.scc_mlp_forward_noalloc(ctypes.byref(self.d), _ptr(self.params), X.shape[0], _ptr(X), _ptr(Y),
+                                              _stream()), "scc_mlp_forward_noalloc")
         return Y
 
     def loss_grad(self, X, T):

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -211,6 +212,17 @@ int guard(F&& f) {
 }
 
 // ---------------------------------------------------------------------------
+// Forward pass without a caller workspace: the two hidden-layer activation
+// buffers live in one file-scope device array (4 MiB on every device the
+// library runs on, held until the process ends).  Host code never passes the
+// array's name to a kernel: its device address is looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr int64_t NOALLOC_FLOATS = (int64_t)1 << 20;
+constexpr int MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+float* noalloc_ptr[MAX_DEVICES] = {};
+
+// ---------------------------------------------------------------------------
 // PCA kernels
 // ---------------------------------------------------------------------------
 // mean[j] = (1/n) sum_i X[i][j]; Xc = X - mean
@@ -311,6 +323,24 @@ int64_t pca_partial_cap(int n, int k) { return std::max<int64_t>((int64_t)n * n,
 }  // namespace
 }  // namespace scc
 
+__device__ __align__(256) float scratch[scc::NOALLOC_FLOATS];
+
+namespace scc {
+namespace {
+// device address of `scratch` on device dev (current), looked up once
+float* noalloc_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void* p = nullptr;
+    hk(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) throw HipError("hipGetSymbolAddress(scratch) returned null");
+    noalloc_ptr[dev] = (float*)p;
+  }
+  return noalloc_ptr[dev];
+}
+}  // namespace
+}  // namespace scc
+
 using namespace scc;
 
 extern "C" {
@@ -335,6 +365,24 @@ int scc_mlp_forward(const scc_mlp_dims* d, const float* params, int n, const flo
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)hip_stream;
     float* h1 = (float*)workspace;
+    float* h2 = h1 + (int64_t)n * M.nh;
+    mlp_forward(M, params, n, X, h1, h2, Y, s);
+    hk(hipStreamSynchronize(s), "sync");
+    return OK;
+  });
+}
+
+int scc_mlp_forward_noalloc(const scc_mlp_dims* d, const float* params, int n, const float* X, float* Y,
+                            void* hip_stream) {
+  if (!valid(d) || !params || n <= 0 || !X || !Y) return EINVAL_;
+  Mlp M(*d);
+  if (2 * (int64_t)n * M.nh > NOALLOC_FLOATS) return ENOMEM_;
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)hip_stream;
+    int dev = 0;
+    hk(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) throw std::invalid_argument("device index");
+    float* h1 = noalloc_scratch(dev);
     float* h2 = h1 + (int64_t)n * M.nh;
     mlp_forward(M, params, n, X, h1, h2, Y, s);
     hk(hipStreamSynchronize(s), "sync");
