@@ -47,7 +47,7 @@ int64_t up(int64_t x, int64_t a = 32) { return (x + a - 1) / a * a; }
 
 struct Sizes {
   int64_t nov, nvt, nst, nlag;
-  int maxsub, cap_lag, cap_k;
+  int maxsub, nkeep, cap_lag, cap_k;
   int nbt, cap_b;        // targets per batched multiplier solve, Krylov capacity of each
   int64_t krylov;        // doubles of the Krylov region (single or batched solves)
   int64_t pool;
@@ -59,12 +59,17 @@ Sizes sizes_for(const Dims& d) {
   s.nvt = s.nov + s.nov * s.nov;
   s.nst = 1 + s.nvt;
   s.nlag = s.nvt + d.ns * (s.nst + 1) + d.npairs();
-  s.maxsub = std::max(40, 12 * d.ns + 24);
+  // Davidson search space: 24 vectors per working root (fewer thick
+  // restarts), at most 24 GB for the vectors and their images; a restart
+  // keeps four Ritz vectors per working root
+  const int nwork = d.ns + 2;
+  s.maxsub = std::max(40, std::min<int>(24 * nwork, (int)(24e9 / (16.0 * up(s.nvt)))));
+  s.nkeep = std::min(s.maxsub / 2, 4 * nwork);
   int64_t p = 0;
   p += up(s.nvt) + up(s.nov);           // D, Dk
   p += 2 * d.ns * up(s.nst);            // R, L
   p += 2 * NDIIS * up(s.nvt) + 3 * up(s.nvt);
-  p += 2 * s.maxsub * up(s.nvt) + 6 * (d.ns + 2) * up(s.nvt) + 2 * up(s.nvt);
+  p += 2 * (int64_t)s.maxsub * up(s.nvt) + (2 * (int64_t)s.nkeep + nwork + 3) * up(s.nvt);
   // recycled GCR spaces: Lagrangian (budget 32 GB) and orbital response
   // Krylov spaces of the multiplier solves share one region (96 GB budget):
   // one target with up to 400 directions, or nbt targets in lockstep
@@ -77,6 +82,10 @@ Sizes sizes_for(const Dims& d) {
   p += 5 * (int64_t)s.nbt * up(s.nlag) + (int64_t)s.nbt * up(s.cap_b);
   s.cap_k = 300;
   p += s.krylov + up(s.cap_lag) + 4 * up(s.nlag);
+  // preconditioner of the multiplier equations: diag(D - omega_k)^-1 L_j for
+  // every (k, j), the Schur vectors of the orthogonality multipliers and
+  // three temporaries of its setup
+  p += (int64_t)d.ns * d.ns * up(s.nst) + (2 * (int64_t)d.npairs() + 3) * up(s.nlag);
   p += 2 * (int64_t)s.cap_k * up(s.nov) + up(s.cap_k) + 4 * up(s.nov);
   p += 64;
   s.pool = p;
@@ -381,6 +390,13 @@ struct DotBatch {
   }
 };
 
+// y += sum_i coef_i X_i for vectors at arbitrary addresses (a few terms)
+void multi_axpy_list(scc_ctx* c, const std::vector<const double*>& X, int64_t n, const std::vector<double>& coef,
+                     double* y) {
+  for (size_t i = 0; i < X.size(); ++i)
+    if (coef[i] != 0.0) launch_axpby(coef[i], X[i], 1.0, y, n, c->s);
+}
+
 // y += sum_i coef_i X[i] (X [k][n]) in one streaming pass
 void multi_axpy(scc_ctx* c, const double* Xb, int k, int64_t n, const std::vector<double>& coef, double* y) {
   if (k == 0) return;
@@ -452,7 +468,7 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
   // keep a nearby root from slowing the convergence of the last requested one
   const int nbuf = 2;
   const int nwork = nroots + nbuf;
-  const int nkeep = std::min(maxsub / 2, 2 * nwork);
+  const int nkeep = std::min(c->sz.nkeep, maxsub / 2);
   const double pfloor = 0.05;
   PoolMark pm(c);
   std::vector<double*> V(maxsub), W(maxsub);
@@ -1130,18 +1146,54 @@ void lag_rhs(scc_ctx* c, const std::vector<int64_t>& offs, int kind, int mm, int
   }
 }
 
+// out = J^T in: one Lagrangian product (single-target program)
+void lag_apply_single(scc_ctx* c, const std::vector<Seg>& segs, const std::vector<int64_t>& offs, const double* in,
+                      double* out) {
+  Model& m = c->m;
+  for (size_t i = 0; i < segs.size(); ++i) {
+    if (segs[i].active)
+      c->put(segs[i].mult, in + offs[i]);
+    else
+      c->fill(c->tp(segs[i].mult), segs[i].n, 0.0);
+  }
+  c->run(m.p_lag);
+  for (size_t i = 0; i < segs.size(); ++i) {
+    if (!segs[i].active) {
+      c->fill(out + offs[i], segs[i].n, 0.0);
+      continue;
+    }
+    c->get(segs[i].adj, out + offs[i]);
+    if (segs[i].comp == 2) c->sym_doubles(out + offs[i]);
+  }
+}
+
 // Preconditioner of the multiplier equations J^T lambda = b (parameter-space
-// residual in, multiplier space out).  Amplitude block: orbital-energy
-// differences.  Each excited state k carries the bordered block
-//     [ (Hbar - E_k)^T   -Lam_k ] [lambda_k]   [f]   (rows of R_k)
-//     [ -R_k^T             0    ] [  mu_k  ] = [g]   (row of E_k)
-// whose leading part is replaced by Dk = diag(D - omega_k) (floored) and
-// solved exactly through its Schur complement:
-//     mu = -(g + R.Dk^-1 f) / (R.Dk^-1 Lam),  lambda = Dk^-1 (f + Lam mu).
-// zeta / O_kl rows: identity.
+// residual in, multiplier space out), a block elimination with three parts.
+//  * Amplitude rows (t) <-> Omega multipliers: orbital-energy differences D.
+//  * Each excited state k: the bordered block
+//        [ (Hbar - E_k)^T   -Lam_k ] [lambda_k]   [f]   (rows of calR_k)
+//        [ -R_k^T             0    ] [  mu_k  ] = [g]   (row of E_k)
+//    solved exactly on the span of the known states and approximately on
+//    the rest: with c_j = R_j . f and the biorthonormal pairs (R_j, L_j),
+//    (Hbar - E_k)^T L_j = (E_j - E_k) L_j, so
+//        mu = -c_k,   lambda = -g L_k + sum_{j != k} c_j / (E_j - E_k) L_j
+//                              + Q diag(D - omega_k)^-1 Q f,
+//    Q removing the components along every L_j (Q f = f - sum_j c_j L_j).
+//  * Orthogonality multipliers gamma_p: they do not enter the zeta rows
+//    directly, only through the blocks above, so they come from the Schur
+//    complement of the zeta rows, S = C^T M^-1 G with G_p = J^T e_gamma_p (the
+//    gradient of O_p over the parameters) and C_p = J e_zeta_p (the zeta
+//    derivative of every constraint): with y = M^-1 v,
+//        gamma = S^-1 (C^T y - v_zeta),   lambda = y - sum_p gamma_p M^-1 G_p.
+// The blocks' couplings (F-bar terms, zeta-scaled X3 derivatives) are left to
+// the Krylov iteration.
 struct LagPrec {
-  std::vector<double*> q;   // Dk^-1 Lam_k per state [1 + nov + nov^2]
-  std::vector<double> den;  // R_k . Dk^-1 Lam_k
+  std::vector<double*> DL;       // diag(D - omega_k)^-1 L_j, [k * ns + j], each [nst]
+  int np = 0;                    // orthogonality multipliers in the Schur step (0: none)
+  std::vector<double*> MG;       // M^-1 G_p, multiplier layout [nlag]
+  std::vector<double*> C;        // C_p, multiplier layout [nlag]
+  std::vector<double> S;         // np x np, row q = C_q
+  int seg_zeta0 = 0;             // first zeta / O segment
 };
 
 void lag_state_dinv(scc_ctx* c, int k, const double* in, double* out) {
@@ -1153,55 +1205,158 @@ void lag_state_dinv(scc_ctx* c, int k, const double* in, double* out) {
   launch_precond(in + 1 + nov, c->D + nov, shift, 0.05, out + 1 + nov, nov * nov, c->s);
 }
 
-LagPrec lag_prec_setup(scc_ctx* c) {
-  LagPrec P;
+// M^-1 of the block-diagonal part (gamma rows left at zero)
+void lag_prec_blocks(scc_ctx* c, const LagPrec& P, const std::vector<Seg>& segs, const std::vector<int64_t>& offs,
+                     const double* in, double* out) {
+  const int64_t nov = c->sz.nov, nst = c->sz.nst;
   const int ns = c->m.d.ns;
   c->fill(c->dsc + 8, 1, 0.0);
-  for (int k = 0; k < ns; ++k) {
-    double* q = c->alloc(c->sz.nst);
-    lag_state_dinv(c, k, c->Lv[k], q);
-    P.q.push_back(q);
-    P.den.push_back(c->dot(c->R[k], q, c->sz.nst));
+  for (size_t i = 0; i < segs.size(); ++i) {
+    const Seg& sg = segs[i];
+    if (sg.kind != 0) continue;
+    const double* Dseg = sg.comp == 1 ? c->D : c->D + nov;
+    launch_precond(in + offs[i], Dseg, 0.0, 0.05, out + offs[i], sg.n, c->s);
   }
+  for (size_t i = 2 + 4 * (size_t)ns; i < segs.size(); ++i) c->fill(out + offs[i], segs[i].n, 0.0);
+  // c_j = R_j . f for every state block, and g, read back together
+  DotBatch d1;
+  std::vector<std::vector<int>> ic(ns, std::vector<int>(ns));
+  std::vector<int> ig(ns);
+  for (int k = 0; k < ns; ++k) {
+    const int64_t sb = offs[2 + 4 * k], eb = offs[2 + 4 * k + 3];
+    for (int j = 0; j < ns; ++j) ic[k][j] = d1.dot(c->R[j], in + sb);
+    ig[k] = d1.value(in + eb);
+  }
+  const auto r1 = d1.run(c, nst);
+  // z = diag(D - omega_k)^-1 (f - sum_j c_j L_j), then R_j . z
+  DotBatch d2;
+  std::vector<std::vector<int>> iz(ns, std::vector<int>(ns));
+  for (int k = 0; k < ns; ++k) {
+    double* z = out + offs[2 + 4 * k];
+    lag_state_dinv(c, k, in + offs[2 + 4 * k], z);
+    std::vector<double> cf(ns);
+    for (int j = 0; j < ns; ++j) cf[j] = -r1[ic[k][j]][0];
+    multi_axpy_list(c, std::vector<const double*>(P.DL.begin() + k * ns, P.DL.begin() + (k + 1) * ns), nst, cf, z);
+    for (int j = 0; j < ns; ++j) iz[k][j] = d2.dot(c->R[j], z);
+  }
+  const auto r2 = d2.run(c, nst);
+  // lambda = Q z - g L_k + sum_{j != k} c_j / (E_j - E_k) L_j,  mu = -c_k
+  for (int k = 0; k < ns; ++k) {
+    double* z = out + offs[2 + 4 * k];
+    const double g = r1[ig[k]][0];
+    std::vector<double> cf(ns);
+    for (int j = 0; j < ns; ++j) {
+      cf[j] = -r2[iz[k][j]][0];
+      if (j == k)
+        cf[j] -= g;
+      else
+        cf[j] += r1[ic[k][j]][0] / (c->E[j] - c->E[k]);
+    }
+    multi_axpy_list(c, std::vector<const double*>(c->Lv.begin(), c->Lv.end()), nst, cf, z);
+    c->set_scalar_ptr(out + offs[2 + 4 * k + 3], -r1[ic[k][k]][0]);
+  }
+}
+
+// Setup at the current solution.  DL by diagonal scaling of the left
+// vectors.  With the SCC constraint active, the Schur step of the
+// orthogonality multipliers: G_p = J^T e_gamma_p by Lagrangian products with
+// unit gamma_p, and C_p (the zeta_p derivative of every constraint) from the
+// residual and right-transformation programs at zeta = e_p and zeta = 0,
+// both affine in zeta, with the X3 states at calR.  The vectors stay in the
+// solver pool of the caller's scope.
+LagPrec lag_prec_setup(scc_ctx* c, const std::vector<Seg>& segs, const std::vector<int64_t>& offs) {
+  LagPrec P;
+  Model& m = c->m;
+  const int ns = m.d.ns, np = m.d.npairs();
+  const int64_t n = c->sz.nlag, nov = c->sz.nov, nst = c->sz.nst, nvt = c->sz.nvt;
+  P.seg_zeta0 = 2 + 4 * ns;
+  c->fill(c->dsc + 8, 1, 0.0);
+  for (int k = 0; k < ns; ++k)
+    for (int j = 0; j < ns; ++j) {
+      double* q = c->alloc(nst);
+      lag_state_dinv(c, k, c->Lv[j], q);
+      P.DL.push_back(q);
+    }
+  if (!c->scc_on || np == 0) return P;
+  P.np = np;
+  for (int p = 0; p < np; ++p) {
+    P.MG.push_back(c->alloc(n));
+    P.C.push_back(c->alloc(n));
+  }
+  {
+    PoolMark tmp_mark(c);
+    double* e = c->alloc(n);
+    double* G = c->alloc(n);
+    for (int p = 0; p < np; ++p) {
+      c->fill(e, n, 0.0);
+      launch_fill(e + offs[P.seg_zeta0 + p], 1, 1.0, c->s);
+      lag_apply_single(c, segs, offs, e, G);
+      lag_prec_blocks(c, P, segs, offs, G, P.MG[p]);
+    }
+    // constraint values at zeta = 0 and at zeta = e_p
+    auto eval = [&](const std::vector<double>& z, double* dst) {
+      c->fill(dst, n, 0.0);
+      set_scc_inputs(c, z, true);
+      c->run(m.p_res);
+      c->get(m.res.O1, dst + offs[0]);
+      c->get(m.res.O2, dst + offs[1]);
+      c->sym_doubles(dst + offs[1]);
+      c->run(m.p_sig_pre);
+      for (int k = 0; k < ns; ++k) {
+        c->put_state(m.vin, c->R[k]);
+        c->run(m.p_sig);
+        c->get(m.sig.s0, dst + offs[2 + 4 * k]);
+        c->get(m.sig.s1, dst + offs[3 + 4 * k]);
+        c->get(m.sig.s2, dst + offs[4 + 4 * k]);
+        c->sym_doubles(dst + offs[4 + 4 * k]);
+      }
+    };
+    double* base = c->alloc(n);
+    eval(std::vector<double>(np, 0.0), base);
+    for (int p = 0; p < np; ++p) {
+      std::vector<double> z(np, 0.0);
+      z[p] = 1.0;
+      eval(z, P.C[p]);
+      c->axpby(-1.0, base, 1.0, P.C[p], n);
+    }
+    // back to the solution's zeta (and its residual / transformation state)
+    set_scc_inputs(c, c->zeta, true);
+    c->run(m.p_res);
+    c->run(m.p_sig_pre);
+  }
+  DotBatch db;
+  std::vector<std::vector<int>> id(np, std::vector<int>(np));
+  for (int q = 0; q < np; ++q)
+    for (int p = 0; p < np; ++p) id[q][p] = db.dot(P.C[q], P.MG[p]);
+  const auto r = db.run(c, n);
+  P.S.assign((size_t)np * np, 0.0);
+  for (int q = 0; q < np; ++q)
+    for (int p = 0; p < np; ++p) P.S[(size_t)q * np + p] = r[id[q][p]][0];
+  (void)nov;
+  (void)nvt;
   return P;
 }
 
 void lag_prec(scc_ctx* c, const LagPrec& P, const std::vector<Seg>& segs, const std::vector<int64_t>& offs,
               const double* in, double* out) {
-  const int64_t nov = c->sz.nov, nst = c->sz.nst;
-  const int ns = c->m.d.ns;
-  c->fill(c->dsc + 8, 1, 0.0);
-  // amplitude block and zeta rows
-  for (size_t i = 0; i < segs.size(); ++i) {
-    const Seg& sg = segs[i];
-    if (sg.kind > 0) continue;
-    if (!sg.active) {
-      c->fill(out + offs[i], sg.n, 0.0);
-    } else if (sg.kind < 0) {
-      c->cp(out + offs[i], in + offs[i], sg.n);
-    } else {
-      const double* Dseg = sg.comp == 1 ? c->D : c->D + nov;
-      launch_precond(in + offs[i], Dseg, 0.0, 0.05, out + offs[i], sg.n, c->s);
-    }
-  }
-  // state blocks with their normalisation border (the border values of all
-  // states read back with one wait)
+  lag_prec_blocks(c, P, segs, offs, in, out);
+  if (!P.np) return;
+  const int np = P.np;
+  const int64_t n = c->sz.nlag;
   DotBatch db;
-  std::vector<int> irf(ns), ig(ns);
-  for (int k = 0; k < ns; ++k) {
-    const int64_t sb = offs[2 + 4 * k], eb = offs[2 + 4 * k + 3];
-    lag_state_dinv(c, k, in + sb, out + sb);
-    irf[k] = db.dot(c->R[k], out + sb);
-    ig[k] = db.value(in + eb);
+  std::vector<int> ic(np), iv(np);
+  for (int q = 0; q < np; ++q) {
+    ic[q] = db.dot(P.C[q], out);
+    iv[q] = db.value(in + offs[P.seg_zeta0 + q]);
   }
-  const auto res = db.run(c, nst);
-  for (int k = 0; k < ns; ++k) {
-    const int64_t sb = offs[2 + 4 * k], eb = offs[2 + 4 * k + 3];
-    const double rf = res[irf[k]][0], g = res[ig[k]][0];
-    const double mu = std::fabs(P.den[k]) > 1e-300 ? -(g + rf) / P.den[k] : 0.0;
-    c->axpby(mu, P.q[k], 1.0, out + sb, nst);
-    c->set_scalar_ptr(out + eb, mu);
-  }
+  const auto r = db.run(c, n);
+  std::vector<double> gam(np);
+  for (int q = 0; q < np; ++q) gam[q] = r[ic[q]][0] - r[iv[q]][0];
+  if (!solve_linear(np, P.S, gam)) return;  // singular Schur complement: block part alone
+  std::vector<double> cf(np);
+  for (int p = 0; p < np; ++p) cf[p] = -gam[p];
+  multi_axpy_list(c, std::vector<const double*>(P.MG.begin(), P.MG.end()), n, cf, out);
+  for (int p = 0; p < np; ++p) c->set_scalar_ptr(out + offs[P.seg_zeta0 + p], gam[p]);
 }
 
 // with the multipliers x of one target: orbital multipliers
@@ -1273,25 +1428,9 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
     off += sg.n;
   }
   lag_rhs(c, offs, kind, mm, nn, b);
-  LagPrec lp = lag_prec_setup(c);
+  LagPrec lp = lag_prec_setup(c, segs, offs);
   auto prec = [&](const double* in, double* out) { lag_prec(c, lp, segs, offs, in, out); };
-  auto apply = [&](const double* in, double* out) {
-    for (size_t i = 0; i < segs.size(); ++i) {
-      if (segs[i].active)
-        c->put(segs[i].mult, in + offs[i]);
-      else
-        c->fill(c->tp(segs[i].mult), segs[i].n, 0.0);
-    }
-    c->run(m.p_lag);
-    for (size_t i = 0; i < segs.size(); ++i) {
-      if (!segs[i].active) {
-        c->fill(out + offs[i], segs[i].n, 0.0);
-        continue;
-      }
-      c->get(segs[i].adj, out + offs[i]);
-      if (segs[i].comp == 2) c->sym_doubles(out + offs[i]);
-    }
-  };
+  auto apply = [&](const double* in, double* out) { lag_apply_single(c, segs, offs, in, out); };
   int iters = 0;
   double rel = 0;
   const int maxg = std::max(c->opt.max_iter, c->rec_lag.cap);
@@ -1368,7 +1507,7 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
     }
   }
   PoolMark pm(c);
-  LagPrec lp = lag_prec_setup(c);
+  LagPrec lp = lag_prec_setup(c, segs, offs);
   auto prec = [&](const double* in, double* out) { lag_prec(c, lp, segs, offs, in, out); };
   // out_j = J^T in_j for the listed slots (at most nbt), other slots zero
   auto applyB = [&](const std::vector<const double*>& in, const std::vector<double*>& out) {

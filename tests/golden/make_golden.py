@@ -5,9 +5,9 @@ Calls only oracle/ and synth_inputs/ (seeded synthetic inputs).  Usage:
     python tests/golden/make_golden.py o6v26 --one-order
 writes tests/golden/<name>.json with energies, zeta, gradients of every
 state and the requested couplings at x = 0.  It also records the oracle's
-own wall time for the whole geometry and for one of its residual
-evaluations at that size (the ratio is the oracle's cost per geometry in
-units of its own residual, which the benchmark's CPU baseline uses).
+own wall time for the whole geometry and for its CCSD ground-state solve
+alone (the ratio is the oracle's cost per geometry in units of its own
+ground-state solve, which the benchmark's CPU baseline uses).
 """
 import json
 import os
@@ -24,19 +24,15 @@ from oracle import cc, scc  # noqa: E402
 from synth_inputs import make_system  # noqa: E402
 
 
-def residual_seconds(S):
+def ground_seconds(S):
+    """Wall time of the oracle's CCSD ground-state solve at x = 0 (the
+    sample the benchmark times at its own workload)."""
     h, L = S.at(np.zeros(S.ncoord))
     ht, gt = torch.as_tensor(h), cc.chol_to_g(torch.as_tensor(L))
-    t1 = torch.zeros((S.v, S.o), dtype=torch.float64)
-    t2 = torch.zeros((S.v, S.o, S.v, S.o), dtype=torch.float64)
-    cc.residual(ht, gt, t1, t2, S.o)
-    n, t = 0, 0.0
-    while t < 2.0 or n < 3:
-        c0 = time.perf_counter()
-        cc.residual(ht, gt, t1, t2, S.o)
-        t += time.perf_counter() - c0
-        n += 1
-    return t / n
+    eps = np.diag(cc.fock(ht, gt, S.o).numpy()).copy()
+    c0 = time.perf_counter()
+    scc.solve_ground(ht, gt, S.o, eps)
+    return time.perf_counter() - c0
 
 
 def main(name, both_orders=True):
@@ -64,7 +60,7 @@ def main(name, both_orders=True):
         else:
             out["nac"][f"{tg[1]},{tg[2]}"] = list(map(float, r["value"]))
     out["oracle_timing"] = dict(threads=threads, solve_seconds=t_solve, targets_seconds=t_targets,
-                                residual_seconds=residual_seconds(S),
+                                ground_seconds=ground_seconds(S),
                                 targets=[list(map(str, t)) for t in targets])
     with open(os.path.join(HERE, f"{name}.json"), "w") as f:
         json.dump(out, f, indent=1)

@@ -65,3 +65,26 @@ def test_fullsize_sigma(full):
     assert abs(out[0] - float(s0)) < 1e-9
     np.testing.assert_allclose(out[1:1 + nov], s1.numpy().ravel(), rtol=0, atol=1e-10)
     np.testing.assert_allclose(out[1 + nov:], s2.numpy().ravel(), rtol=0, atol=1e-10)
+
+
+def test_fullsize_left_adjoint(full):
+    """Left transformation at o10v90 (zeta X3 terms on): for random right
+    vectors r, <sigma_L(l), r> equals <l, sigma(r)> with sigma the oracle's
+    right transformation (the defining property of the transpose, which
+    every element of sigma_L enters with a random weight)."""
+    S, ctx, h, g, t1, t2, states, zeta, vec = full
+    t = np.concatenate([t1.ravel(), t2.ravel()])
+    ctx.eval_residual(t, zeta, np.stack([_flat(r) for r in states]))
+    l1, l2 = random_amplitudes(S.o, S.v, seed=21, scale=0.02)
+    lvec = _flat((0.4, l1, l2))
+    left = ctx.eval_left(lvec).cpu().numpy()
+    rs = [tuple(T(x) for x in r) for r in states]
+    r1, r2 = random_amplitudes(S.o, S.v, seed=23, scale=0.02)
+    r = (0.3, r1, r2)
+    t0 = time.time()
+    s0, s1, s2 = cc.sigma(T(h), g, T(t1), T(t2), S.o, T(r[0]), T(r[1]), T(r[2]), T(zeta), rs)
+    print(f"  oracle sigma {time.time() - t0:.1f}s", flush=True)
+    ref = float(lvec @ _flat((float(s0), s1.numpy(), s2.numpy())))
+    val = float(left @ _flat(r))
+    print(f"  <l, sigma(r)> {ref:.15e}  <sigma_L(l), r> {val:.15e}", flush=True)
+    assert abs(val - ref) < 1e-11 * max(1.0, abs(ref))
