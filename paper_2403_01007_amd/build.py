@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["ir.cpp", "model.cpp", "exec.hip", "vec.hip", "scc.cpp", "learn.hip"]
+SRC = ["ir.cpp", "model.cpp", "exec.hip", "vec.hip", "singles.hip", "scc.cpp", "learn.hip"]
 OUT = os.path.join(HERE, "libscc.so")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

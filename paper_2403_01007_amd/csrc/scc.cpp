@@ -24,6 +24,7 @@
 #include "exec.hpp"
 #include "vec.hpp"
 #include "model.hpp"
+#include "singles.hpp"
 #include "smalllinalg.hpp"
 
 using namespace scc;
@@ -59,12 +60,12 @@ Sizes sizes_for(const Dims& d) {
   s.nvt = s.nov + s.nov * s.nov;
   s.nst = 1 + s.nvt;
   s.nlag = s.nvt + d.ns * (s.nst + 1) + d.npairs();
-  // Davidson search space: 24 vectors per working root (fewer thick
-  // restarts), at most 24 GB for the vectors and their images; a restart
-  // keeps four Ritz vectors per working root
+  // Davidson search space: 16 vectors per working root, at most 24 GB for
+  // the vectors and their images; a thick restart keeps three Ritz vectors
+  // per working root
   const int nwork = d.ns + 2;
-  s.maxsub = std::max(40, std::min<int>(24 * nwork, (int)(24e9 / (16.0 * up(s.nvt)))));
-  s.nkeep = std::min(s.maxsub / 2, 4 * nwork);
+  s.maxsub = std::max(40, std::min<int>(16 * nwork, (int)(24e9 / (16.0 * up(s.nvt)))));
+  s.nkeep = std::min(s.maxsub / 2, 3 * nwork);
   int64_t p = 0;
   p += up(s.nvt) + up(s.nov);           // D, Dk
   p += 2 * d.ns * up(s.nst);            // R, L
@@ -86,6 +87,9 @@ Sizes sizes_for(const Dims& d) {
   // every (k, j), the Schur vectors of the orthogonality multipliers and
   // three temporaries of its setup
   p += (int64_t)d.ns * d.ns * up(s.nst) + (2 * (int64_t)d.npairs() + 3) * up(s.nlag);
+  // singles preconditioner: matrix, eigenvectors, eigenvalues, orbital
+  // energies, eigensolver work space, temporaries of the shifted solves
+  p += 2 * up(s.nov * s.nov) + up(s.nov) + up(d.n) + up(jacobi_work_doubles((int)s.nov)) + 2 * up(s.nov);
   p += 2 * (int64_t)s.cap_k * up(s.nov) + up(s.cap_k) + 4 * up(s.nov);
   p += 64;
   s.pool = p;
@@ -138,6 +142,19 @@ struct scc_ctx {
   std::vector<double*> R, Lv; // states [r0 | r1 | r2]
   double* kbar = nullptr;
   double* dsc = nullptr;      // device scalars
+  // singles preconditioner: eigenvectors U [nov][nov] and eigenvalues w
+  // [nov] of the singlet singles matrix of the current geometry (its A is
+  // overwritten by the eigensolver), orbital energies on the device
+  double* cisA = nullptr;
+  double* cisU = nullptr;
+  double* cisW = nullptr;
+  double* eps_d = nullptr;
+  double* cis_work = nullptr;
+  double* cis_tmp = nullptr;
+  // y = U diag(1 / floor(w - shift)) U^T x on the singles block
+  void singles_solve(const double* x, double shift, double fl, double* y) {
+    launch_eig_shift_solve(cisU, cisW, (int)sz.nov, shift, fl, x, y, cis_tmp, s);
+  }
   Recycler rec_lag, rec_k;    // recycled Krylov spaces of the multiplier solves
   std::vector<double> eps;
   bool have_h = false, have_ground = false, have_excited = false, have_mult = false;
@@ -241,7 +258,8 @@ void scc_ctx::log(const char* fmt, ...) {
 namespace {
 
 // ---------------------------------------------------------------------------
-// ground state: Jacobi steps with the orbital-energy preconditioner + DIIS
+// ground state: quasi-Newton steps (orbital-energy differences on the
+// doubles, the inverse singles matrix on the singles) + DIIS
 // ---------------------------------------------------------------------------
 int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
   Model& m = c->m;
@@ -282,6 +300,7 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
       best = rn;
     }
     launch_precond(r, c->D, 0.0, 1e-8, e, nvt, c->s);
+    c->singles_solve(r, 0.0, 1e-8, e);
     int slot = head;
     head = (head + 1) % NDIIS;
     nh = std::min(nh + 1, NDIIS);
@@ -507,15 +526,15 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     add_vector(q);
   }
   if (nv < nwork) {
-    // unit vectors on the smallest singles denominators
-    std::vector<double> dh(nov);
-    c->xfer(dh.data(), c->D, nov * sizeof(double), hipMemcpyDeviceToHost);
+    // the lowest eigenvectors of the singlet singles matrix
+    std::vector<double> wh(nov);
+    c->xfer(wh.data(), c->cisW, nov * sizeof(double), hipMemcpyDeviceToHost);
     std::vector<int> idx(nov);
     for (int64_t i = 0; i < nov; ++i) idx[i] = (int)i;
-    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return dh[a] < dh[b]; });
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return wh[a] < wh[b]; });
     for (int64_t k = 0; k < nov && nv < std::max(nwork, nroots + 2); ++k) {
       c->fill(q, nvt, 0.0);
-      launch_fill(q + idx[k], 1, 1.0, c->s);
+      launch_eig_column(c->cisU, (int)nov, idx[k], q, c->s);
       add_vector(q);
     }
   }
@@ -551,21 +570,18 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     for (int i = 0; i < nv; ++i) ord[i] = i;
     std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
     const int nr_now = std::min(nw_, nv);
-    const int nx = std::min(nkeep, nv);
-    // eigenvectors of the Ritz values kept only
+    const int nx = std::max(nr_now, std::min(nkeep, nv));
+    // Ritz vectors Xr[k] = V y_k and images Xw[k] = W y_k of the k-th lowest
+    // Ritz value: the working roots every iteration, the rest of the kept
+    // ones only for a thick restart
     Y.assign(nv * nv, 0.0);
-    {
-      std::vector<cplx> y;
-      for (int k = 0; k < nx; ++k) {
-        eig_nonsym_vector(nv, Gs, w[ord[k]], y);
-        for (int j = 0; j < nv; ++j) Y[j * nv + ord[k]] = y[j];
-      }
-    }
-    double maxres = 0;
     std::vector<double> th(nx);
     std::vector<char> conv(nx, 0), cplx_k(nx, 0);
-    for (int k = 0; k < nx; ++k) {
-      int col = ord[k];
+    auto ritz = [&](int k) {
+      std::vector<cplx> yc;
+      const int col = ord[k];
+      eig_nonsym_vector(nv, Gs, w[col], yc);
+      for (int j = 0; j < nv; ++j) Y[j * nv + col] = yc[j];
       th[k] = w[col].real();
       // a complex-conjugate Ritz pair contributes Re(y) and Im(y)
       const bool cplx_pair = std::fabs(w[col].imag()) > 1e-10 * std::max(1.0, std::fabs(w[col].real()));
@@ -573,7 +589,7 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       std::vector<double> y(nv);
       double yn = 0;
       for (int j = 0; j < nv; ++j) {
-        y[j] = use_imag ? Y[j * nv + col].imag() : Y[j * nv + col].real();
+        y[j] = use_imag ? yc[j].imag() : yc[j].real();
         yn += y[j] * y[j];
       }
       yn = std::sqrt(yn);
@@ -587,7 +603,9 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
         c->axpby(-th[k], Xr[k], 1.0, Rs[k], nvt);
         cplx_k[k] = cplx_pair;
       }
-    }
+    };
+    for (int k = 0; k < nr_now; ++k) ritz(k);
+    double maxres = 0;
     // residual norms of the working roots, read back together
     {
       DotBatch db;
@@ -660,6 +678,7 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
       if (!conv[k]) ++nnew;
     if (nv + nnew > maxsub) {
       // thick restart on the lowest nkeep Ritz vectors (orthonormalised)
+      for (int k = nr_now; k < nx; ++k) ritz(k);
       nv = 0;
       for (int k = 0; k < nx; ++k) {
         for (int pass = 0; pass < 2; ++pass) {
@@ -681,8 +700,10 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     }
     for (int k = 0; k < nr_now; ++k) {
       if (conv[k]) continue;
-      // (D - omega)^-1 with omega = theta - E0 (Hbar carries E0 on its diagonal)
+      // (D - omega)^-1 with omega = theta - E0 (Hbar carries E0 on its
+      // diagonal); on the singles, the shifted inverse of the singles matrix
       launch_precond(Rs[k], c->D, th[k] - c->E0, pfloor, q, nvt, c->s);
+      c->singles_solve(Rs[k], th[k] - c->E0, pfloor, q);
       c->sym_doubles(q + nov);
       if (nv < maxsub) add_vector(q);
     }
@@ -1201,7 +1222,7 @@ void lag_state_dinv(scc_ctx* c, int k, const double* in, double* out) {
   double* dzero = c->dsc + 8;
   const double shift = c->E[k] - c->E0;
   launch_precond(in, dzero, shift, 0.05, out, 1, c->s);
-  launch_precond(in + 1, c->D, shift, 0.05, out + 1, nov, c->s);
+  c->singles_solve(in + 1, shift, 0.05, out + 1);
   launch_precond(in + 1 + nov, c->D + nov, shift, 0.05, out + 1 + nov, nov * nov, c->s);
 }
 
@@ -1214,8 +1235,10 @@ void lag_prec_blocks(scc_ctx* c, const LagPrec& P, const std::vector<Seg>& segs,
   for (size_t i = 0; i < segs.size(); ++i) {
     const Seg& sg = segs[i];
     if (sg.kind != 0) continue;
-    const double* Dseg = sg.comp == 1 ? c->D : c->D + nov;
-    launch_precond(in + offs[i], Dseg, 0.0, 0.05, out + offs[i], sg.n, c->s);
+    if (sg.comp == 1)
+      c->singles_solve(in + offs[i], 0.0, 0.05, out + offs[i]);
+    else
+      launch_precond(in + offs[i], c->D + nov, 0.0, 0.05, out + offs[i], sg.n, c->s);
   }
   for (size_t i = 2 + 4 * (size_t)ns; i < segs.size(); ++i) c->fill(out + offs[i], segs[i].n, 0.0);
   // c_j = R_j . f for every state block, and g, read back together
@@ -1871,6 +1894,12 @@ int scc_create(const scc_dims* dims, const scc_options* opts, void* workspace, s
     c->rec_k.cap = c->sz.cap_k;
     c->rec_k.U = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
     c->rec_k.C = c->alloc((int64_t)c->sz.cap_k * up(c->sz.nov));
+    c->cisA = c->alloc(c->sz.nov * c->sz.nov);
+    c->cisU = c->alloc(c->sz.nov * c->sz.nov);
+    c->cisW = c->alloc(c->sz.nov);
+    c->eps_d = c->alloc(dd.n);
+    c->cis_work = c->alloc(jacobi_work_doubles((int)c->sz.nov));
+    c->cis_tmp = c->alloc(c->sz.nov);
     c->pool_base = c->pool_used;
     // constants
     Model& m = c->m;
@@ -2084,6 +2113,11 @@ int install_mo_hamiltonian_impl(scc_ctx* c, double e_nuc) {
     }
     c->xfer(c->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice);
     c->xfer(c->Dk, Dk.data(), Dk.size() * sizeof(double), hipMemcpyHostToDevice);
+    // singles preconditioner of this geometry
+    c->xfer(c->eps_d, c->eps.data(), N * sizeof(double), hipMemcpyHostToDevice);
+    launch_cis_matrix(c->tp(m.L), J, o, v, c->eps_d, c->cisA, c->s);
+    const int sweeps = sym_eig_jacobi(c->cisA, c->cisU, c->cisW, (int)nov, c->cis_work, c->s);
+    c->log(" singles matrix diagonalised in %d Jacobi sweeps\n", sweeps);
     // every geometry starts cold: t = 0 (the first Jacobi step is MP2), zeta = 0
     c->fill(c->tp(m.t1), nov, 0.0);
     c->fill(c->tp(m.t2), nov * nov, 0.0);

@@ -380,3 +380,38 @@ def test_failure_paths():
     with pytest.raises(SccError) as e:
         ctx.densities(1, 0, 0)
     assert e.value.code == -1
+
+
+def test_o6v26_batched_targets_against_stored_oracle():
+    """Three states, their three gradients and the three couplings (0,1),
+    (0,2), (1,2) over six coordinates, all targets solved in lockstep by
+    scc_gradients_and_couplings (the path the benchmark times), against
+    values written by tests/golden/make_golden.py, which calls only the
+    oracle (its Davidson EOM path at this size)."""
+    path = os.path.join(HERE, "golden", "o6v26.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/o6v26.json not written yet")
+    with open(path) as f:
+        ref = json.load(f)
+    from paper_2403_01007_amd import Context
+    S = make_system("o6v26")
+    assert (S.seed, S.reading, S.o, S.v, S.nj) == (ref["seed"], ref["reading"], ref["o"], ref["v"], ref["nj"])
+    print("[o6v26 golden, batched targets]", flush=True)
+    h, L = S.at(np.zeros(S.ncoord))
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
+    ctx.set_hamiltonian(h, L)
+    E, z, _ = ctx.excited()
+    e0 = float(ctx.get(3).cpu()[0])
+    assert abs(e0 - ref["E0"]) < E_TOL
+    assert np.abs(E - np.asarray(ref["E"])).max() < E_TOL
+    assert np.abs(z - np.asarray(ref["zeta"])).max() < 1e-7
+    states = list(range(S.nstates))
+    g, d, _ = ctx.gradients_and_couplings(states, list(S.nacs), S.dh, S.dL)
+    for k in states:
+        err = np.abs(g[k] - np.asarray(ref["grad"][str(k)])).max()
+        print(f"  grad {k} max err {err:.2e}", flush=True)
+        assert err < G_TOL
+    for i, (m, n) in enumerate(S.nacs):
+        err = np.abs(d[i] - np.asarray(ref["nac"][f"{m},{n}"])).max()
+        print(f"  nac {(m, n)} max err {err:.2e}", flush=True)
+        assert err < G_TOL
