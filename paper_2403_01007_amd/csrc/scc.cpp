@@ -87,6 +87,9 @@ Sizes sizes_for(const Dims& d) {
   // every (k, j), the Schur vectors of the orthogonality multipliers and
   // three temporaries of its setup
   p += (int64_t)d.ns * d.ns * up(s.nst) + (2 * (int64_t)d.npairs() + 3) * up(s.nlag);
+  // Anderson history of the SCC macro iteration (6 iterates: mixed states
+  // and residuals) and the X3 input states
+  p += (2 * 6 + 1) * (int64_t)d.ns * up(s.nst);
   // singles preconditioner: matrix, eigenvectors, eigenvalues, orbital
   // energies, eigensolver work space, temporaries of the shifted solves
   p += 2 * up(s.nov * s.nov) + up(s.nov) + up(d.n) + up(jacobi_work_doubles((int)s.nov)) + 2 * up(s.nov);
@@ -840,35 +843,68 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
     return excited_at_fixed_zeta(c, tol, maxit, true, iters, true);
   }
   if (use_scc) {
+    // The SCC macro iteration is a fixed-point map x -> G(x) on x = (zeta,
+    // X3 states): the ground and excited states are solved at (zeta, X3),
+    // giving right vectors R' and overlaps O; G(x) = (zeta - J^-1 O, R') with
+    // J = dO/dzeta at fixed X3 (finite differences once, or the previous
+    // solve's).  Its fixed point is the SCC solution.  Anderson mixing of the
+    // last NAND iterates (the combination of the G(x_i) whose residuals
+    // G(x_i) - x_i have the least norm, weights summing to one) replaces the
+    // plain step x <- G(x): the X3 states lag one iteration behind the
+    // states they are built from, and the plain iteration converges only
+    // linearly.
+    constexpr int NAND = 6;
     const int64_t nst = c->sz.nst;
     PoolMark pm(c);
-    std::vector<double*> prev(ns);
-    for (int k = 0; k < ns; ++k) prev[k] = c->alloc(nst);
+    std::vector<double*> Rx(ns);                                 // X3 input states of this iteration
+    for (int k = 0; k < ns; ++k) {
+      Rx[k] = c->alloc(nst);
+      c->cp(Rx[k], c->R[k], nst);
+    }
+    std::vector<std::vector<double*>> Rg(NAND, std::vector<double*>(ns)), Rf = Rg;
+    for (int i = 0; i < NAND; ++i)
+      for (int k = 0; k < ns; ++k) {
+        Rg[i][k] = c->alloc(nst);
+        Rf[i][k] = c->alloc(nst);
+      }
+    std::vector<std::vector<double>> zg(NAND), zf(NAND);
+    std::vector<double> Bm(NAND * NAND, 0.0);
+    int nh = 0, head = 0;
     std::vector<double>& Jz = c->Jz;
-    std::vector<double> z = c->zeta, Oprev, zprev;
+    std::vector<double> z = c->zeta;
     bool conv = false;
-    double omax_prev = 1.0;
+    double omax_prev = 1.0, best = 1e300;
     for (int it = 0; it < c->opt.max_iter && !conv; ++it) {
       // inexact inner solves while the constraint is far from satisfied;
       // the pass that is the base point of a finite-difference Jacobian is
       // tight (a Jacobian carried over from a previous solve needs none)
       const bool fd_base = it == 0 && Jz.empty();
       const double tol_it = fd_base ? tol : std::max(tol, std::min(1e-5, 1e-3 * omax_prev));
-      for (int k = 0; k < ns; ++k) c->cp(prev[k], c->R[k], nst);
-      set_scc_inputs(c, z, true);
+      for (size_t p = 0; p < c->m.zeta.size(); ++p) c->set_scalar(c->m.zeta[p], z[p]);
+      for (int k = 0; k < ns; ++k) c->put_state(c->m.xs[k], Rx[k]);
       rc = excited_at_fixed_zeta(c, tol_it, maxit, true, iters, false);
       if (rc) return rc;
       std::vector<double> O = pair_overlaps(c);
+      // residual of the X3 states: R' - Rx (new slot of the history)
+      const int slot = head;
+      head = (head + 1) % NAND;
+      nh = std::min(nh + 1, NAND);
       double dR = 0, omax = 0;
-      for (int k = 0; k < ns; ++k) {
-        PoolMark pk(c);
-        double* dif = c->alloc(nst);
-        c->cp(dif, c->R[k], nst);
-        c->axpby(-1.0, prev[k], 1.0, dif, nst);
-        dR = std::max(dR, std::sqrt(c->dot(dif, dif, nst)));
+      {
+        DotBatch db;
+        std::vector<int> id(ns);
+        for (int k = 0; k < ns; ++k) {
+          c->cp(Rg[slot][k], c->R[k], nst);
+          c->cp(Rf[slot][k], c->R[k], nst);
+          c->axpby(-1.0, Rx[k], 1.0, Rf[slot][k], nst);
+          id[k] = db.dot(Rf[slot][k], Rf[slot][k]);
+        }
+        const auto r = db.run(c, nst);
+        for (int k = 0; k < ns; ++k) dR = std::max(dR, std::sqrt(r[id[k]][0]));
       }
       for (double x : O) omax = std::max(omax, std::fabs(x));
-      c->log(" scc it %2d  max|O| %.3e  |dR| %.3e  zeta0 %.8f  (inner tol %.1e)\n", it, omax, dR, z[0], tol_it);
+      c->log(" scc it %2d  max|O| %.3e  |dR| %.3e  zeta0 %.8f  (inner tol %.1e, history %d)\n", it, omax, dR, z[0],
+             tol_it, nh);
       omax_prev = omax;
       if (omax < tol_overlap && dR < 10 * tol && tol_it <= tol) {
         conv = true;
@@ -886,13 +922,12 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
           c->cp(keepR[k], c->R[k], nst);
           c->cp(keepL[k], c->Lv[k], nst);
         }
-        // the displaced solves need O to ~1e-8 only (h = 1e-4; Broyden
-        // updates refine the Jacobian afterwards)
+        // the displaced solves need O to ~1e-8 only (h = 1e-4)
         const double tol_fd = std::max(tol_it, 1e-8);
         for (int p = 0; p < np; ++p) {
           std::vector<double> zp = z;
           zp[p] += h;
-          set_scc_inputs(c, zp, false);
+          for (size_t q = 0; q < c->m.zeta.size(); ++q) c->set_scalar(c->m.zeta[q], zp[q]);
           rc = excited_at_fixed_zeta(c, tol_fd, maxit, true, iters, false);
           if (rc) return rc;
           std::vector<double> Op = pair_overlaps(c);
@@ -902,27 +937,73 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
             c->cp(c->Lv[k], keepL[k], nst);
           }
         }
-      } else if (!Oprev.empty()) {
-        // Broyden update of the Jacobian
-        std::vector<double> dz(np), dO(np);
-        double dzz = 0;
-        for (int p = 0; p < np; ++p) {
-          dz[p] = z[p] - zprev[p];
-          dO[p] = O[p] - Oprev[p];
-          dzz += dz[p] * dz[p];
-        }
-        if (dzz > 0)
-          for (int q = 0; q < np; ++q) {
-            double jd = 0;
-            for (int p = 0; p < np; ++p) jd += Jz[q * np + p] * dz[p];
-            for (int p = 0; p < np; ++p) Jz[q * np + p] += (dO[q] - jd) * dz[p] / dzz;
-          }
       }
       std::vector<double> step = O;
       if (!solve_linear(np, Jz, step)) throw SccError(SCC_ESINGULAR, "zeta Jacobian singular");
-      Oprev = O;
-      zprev = z;
-      for (int p = 0; p < np; ++p) z[p] -= step[p];
+      zg[slot].resize(np);
+      zf[slot].resize(np);
+      for (int p = 0; p < np; ++p) {
+        zg[slot][p] = z[p] - step[p];
+        zf[slot][p] = -step[p];
+      }
+      // a clear setback restarts the history from this iterate
+      if (omax < best) {
+        best = omax;
+      } else if (omax > 10 * best) {
+        nh = 1;
+        best = omax;
+        for (int i = 0; i < NAND; ++i)
+          if (i != slot) zg[i].clear();
+      }
+      // Gram matrix of the residuals (R parts on the device, zeta parts here)
+      {
+        DotBatch db;
+        std::vector<std::vector<int>> id(NAND, std::vector<int>(ns, -1));
+        for (int i = 0; i < NAND; ++i) {
+          if (zg[i].empty() || (nh < NAND && ((slot - i + NAND) % NAND) >= nh)) continue;
+          for (int k = 0; k < ns; ++k) id[i][k] = db.dot(Rf[slot][k], Rf[i][k]);
+        }
+        const auto r = db.run(c, nst);
+        for (int i = 0; i < NAND; ++i) {
+          if (id[i][0] < 0) continue;
+          double v = 0;
+          for (int k = 0; k < ns; ++k) v += r[id[i][k]][0];
+          for (int p = 0; p < np; ++p) v += zf[slot][p] * zf[i][p];
+          Bm[slot * NAND + i] = Bm[i * NAND + slot] = v;
+        }
+      }
+      std::vector<int> use;
+      for (int d = 0; d < nh; ++d) use.push_back((slot - d + NAND) % NAND);
+      const int nu = (int)use.size(), n1 = nu + 1;
+      std::vector<double> A(n1 * n1, 0.0), w(n1, 0.0);
+      double sc = 0;
+      for (int i = 0; i < nu; ++i) sc = std::max(sc, Bm[use[i] * NAND + use[i]]);
+      if (!(sc > 0)) sc = 1;
+      for (int i = 0; i < nu; ++i) {
+        for (int j = 0; j < nu; ++j) A[i * n1 + j] = Bm[use[i] * NAND + use[j]] / sc;
+        A[i * n1 + nu] = A[nu * n1 + i] = -1.0;
+      }
+      w[nu] = -1.0;
+      if (nu == 1 || !solve_linear(n1, A, w)) {
+        std::fill(w.begin(), w.end(), 0.0);
+        w[0] = 1.0;  // plain step from the newest iterate
+      }
+      // next iterate: sum_i w_i G(x_i)
+      for (int p = 0; p < np; ++p) {
+        double v = 0;
+        for (int i = 0; i < nu; ++i) v += w[i] * zg[use[i]][p];
+        z[p] = v;
+      }
+      for (int k = 0; k < ns; ++k) {
+        std::vector<const double*> src(nu);
+        std::vector<double> cf(nu);
+        for (int i = 0; i < nu; ++i) {
+          src[i] = Rg[use[i]][k];
+          cf[i] = w[i];
+        }
+        c->fill(Rx[k], nst, 0.0);
+        multi_axpy_list(c, src, nst, cf, Rx[k]);
+      }
     }
     c->zeta = z;
     if (!conv) {
