@@ -568,7 +568,8 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
     for (int i = 0; i < nv; ++i)
       for (int j = 0; j < nv; ++j) Gs[i * nv + j] = G[i * maxsub + j];
     std::vector<cplx> w, Y;
-    if (!eig_nonsym(nv, Gs, w, Y, false)) throw SccError(SCC_ENOCONV, "subspace eigensolver failed");
+    if (!eig_nonsym_real(nv, Gs, w) && !eig_nonsym(nv, Gs, w, Y, false))
+      throw SccError(SCC_ENOCONV, "subspace eigensolver failed");
     std::vector<int> ord(nv);
     for (int i = 0; i < nv; ++i) ord[i] = i;
     std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });

@@ -1,7 +1,8 @@
 // Small dense linear algebra for the solvers' subspace problems (dimensions
-// of a few tens): pivoted Gaussian elimination and a nonsymmetric
-// eigensolver (Householder reduction to Hessenberg form, complex
-// single-shift QR with Wilkinson shifts, eigenvectors by inverse iteration).
+// of a few tens): pivoted Gaussian elimination, nonsymmetric eigensolvers
+// (Householder reduction to Hessenberg form, then real double-shift QR, or
+// complex single-shift QR with Wilkinson shifts; eigenvectors by inverse
+// iteration) and a cyclic Jacobi symmetric eigensolver.
 #pragma once
 #include <algorithm>
 #include <cmath>
@@ -67,7 +68,13 @@ inline bool solve_complex(int n, std::vector<cplx> A, std::vector<cplx>& b) {
 // One eigenvector of A (n x n, row-major) for the eigenvalue lam, by inverse
 // iteration: one LU factorisation of A - lam' (lam nudged off the exact
 // eigenvalue), three solves; normalised, largest component real positive.
+inline void eig_nonsym_vector_real(int n, const std::vector<double>& A, double lam, std::vector<cplx>& x);
+
 inline void eig_nonsym_vector(int n, const std::vector<double>& A, cplx lam, std::vector<cplx>& x) {
+  if (lam.imag() == 0.0) {
+    eig_nonsym_vector_real(n, A, lam.real(), x);
+    return;
+  }
   double anorm = 0;
   for (int i = 0; i < n * n; ++i) anorm = std::max(anorm, std::fabs(A[i]));
   lam += cplx(1e-13 * (anorm + 1.0), 0.0);
@@ -115,6 +122,57 @@ inline void eig_nonsym_vector(int n, const std::vector<double>& A, cplx lam, std
     if (std::abs(x[i]) > std::abs(x[im])) im = i;
   const cplx ph = std::abs(x[im]) > 0 ? std::conj(x[im]) / std::abs(x[im]) : cplx(1.0);
   for (int i = 0; i < n; ++i) x[i] *= ph;
+}
+
+// The same for a real eigenvalue, in real arithmetic (a quarter of the work).
+inline void eig_nonsym_vector_real(int n, const std::vector<double>& A, double lam, std::vector<cplx>& xc) {
+  double anorm = 0;
+  for (int i = 0; i < n * n; ++i) anorm = std::max(anorm, std::fabs(A[i]));
+  lam += 1e-13 * (anorm + 1.0);
+  std::vector<double> M(A);
+  for (int i = 0; i < n; ++i) M[(size_t)i * n + i] -= lam;
+  std::vector<int> piv(n);
+  bool ok = true;
+  for (int k = 0; k < n && ok; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(M[(size_t)i * n + k]) > std::fabs(M[(size_t)p * n + k])) p = i;
+    piv[k] = p;
+    if (M[(size_t)p * n + k] == 0.0) {
+      ok = false;
+      break;
+    }
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(M[(size_t)k * n + j], M[(size_t)p * n + j]);
+    for (int i = k + 1; i < n; ++i) {
+      const double f = M[(size_t)i * n + k] / M[(size_t)k * n + k];
+      M[(size_t)i * n + k] = f;
+      for (int j = k + 1; j < n; ++j) M[(size_t)i * n + j] -= f * M[(size_t)k * n + j];
+    }
+  }
+  std::vector<double> x(n);
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.1 * i;
+  for (int it = 0; it < 3 && ok; ++it) {
+    for (int k = 0; k < n; ++k) {
+      if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+      for (int i = k + 1; i < n; ++i) x[i] -= M[(size_t)i * n + k] * x[k];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double sum = x[i];
+      for (int j = i + 1; j < n; ++j) sum -= M[(size_t)i * n + j] * x[j];
+      x[i] = sum / M[(size_t)i * n + i];
+    }
+    double nr = 0;
+    for (double z : x) nr += z * z;
+    nr = std::sqrt(nr);
+    for (double& z : x) z /= nr;
+  }
+  int im = 0;
+  for (int i = 1; i < n; ++i)
+    if (std::fabs(x[i]) > std::fabs(x[im])) im = i;
+  const double sg = x[im] < 0 ? -1.0 : 1.0;
+  xc.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) xc[i] = sg * x[i];
 }
 
 // Eigenvalues of a real non-symmetric matrix (Hessenberg reduction, shifted
@@ -213,6 +271,131 @@ inline bool eig_nonsym(int n, const std::vector<double>& A, std::vector<cplx>& w
   for (int k = 0; k < n; ++k) {
     eig_nonsym_vector(n, A, w[k], x);
     for (int i = 0; i < n; ++i) V[i * n + k] = x[i];
+  }
+  return true;
+}
+
+// Eigenvalues of a real nonsymmetric matrix in real arithmetic: Householder
+// reduction to upper Hessenberg form, then implicitly shifted QR steps with
+// the two eigenvalues of the trailing 2 x 2 block as a double shift (a 3 x 3
+// Householder reflector introduces the bulge, further reflectors chase it down
+// the subdiagonal), with deflation at negligible subdiagonal elements; a
+// trailing 2 x 2 block gives a real pair or a complex-conjugate pair.  About
+// a quarter of the work of the complex single-shift iteration.  Returns false
+// if some eigenvalue needs more than 60 steps.
+inline bool eig_nonsym_real(int n, const std::vector<double>& A, std::vector<cplx>& w) {
+  std::vector<double> H(A);
+  auto h = [&](int i, int j) -> double& { return H[(size_t)i * n + j]; };
+  for (int k = 0; k + 2 < n; ++k) {
+    double alpha = 0;
+    for (int i = k + 1; i < n; ++i) alpha += h(i, k) * h(i, k);
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    std::vector<double> u(n, 0.0);
+    for (int i = k + 1; i < n; ++i) u[i] = h(i, k);
+    u[k + 1] += h(k + 1, k) >= 0 ? alpha : -alpha;
+    double un = 0;
+    for (int i = k + 1; i < n; ++i) un += u[i] * u[i];
+    if (un == 0.0) continue;
+    for (int j = 0; j < n; ++j) {  // H = (I - 2 u u^T / un) H
+      double sdot = 0;
+      for (int i = k + 1; i < n; ++i) sdot += u[i] * h(i, j);
+      sdot *= 2.0 / un;
+      for (int i = k + 1; i < n; ++i) h(i, j) -= u[i] * sdot;
+    }
+    for (int i = 0; i < n; ++i) {  // H = H (I - 2 u u^T / un)
+      double sdot = 0;
+      for (int j = k + 1; j < n; ++j) sdot += h(i, j) * u[j];
+      sdot *= 2.0 / un;
+      for (int j = k + 1; j < n; ++j) h(i, j) -= sdot * u[j];
+    }
+    for (int i = k + 2; i < n; ++i) h(i, k) = 0.0;
+  }
+  w.assign(n, 0.0);
+  // P = I - 2 v v^T / (v.v) applied to rows r0..r0+m-1 (columns c0..c1) and
+  // to the same columns (rows q0..q1); v of length m (2 or 3)
+  auto reflect = [&](const double* v, int m, int r0, int c0, int c1, int q0, int q1) {
+    double vv = 0;
+    for (int i = 0; i < m; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) return;
+    const double f = 2.0 / vv;
+    for (int j = c0; j <= c1; ++j) {
+      double sdot = 0;
+      for (int i = 0; i < m; ++i) sdot += v[i] * h(r0 + i, j);
+      sdot *= f;
+      for (int i = 0; i < m; ++i) h(r0 + i, j) -= v[i] * sdot;
+    }
+    for (int i = q0; i <= q1; ++i) {
+      double sdot = 0;
+      for (int j = 0; j < m; ++j) sdot += h(i, r0 + j) * v[j];
+      sdot *= f;
+      for (int j = 0; j < m; ++j) h(i, r0 + j) -= sdot * v[j];
+    }
+  };
+  // Householder vector v with (I - 2 v v^T / v.v) x = -+|x| e1
+  auto house = [](const double* x, int m, double* v) {
+    double nx = 0;
+    for (int i = 0; i < m; ++i) nx += x[i] * x[i];
+    nx = std::sqrt(nx);
+    for (int i = 0; i < m; ++i) v[i] = x[i];
+    v[0] += x[0] >= 0 ? nx : -nx;
+  };
+  int hi = n - 1, its = 0;
+  while (hi >= 0) {
+    int l = hi;
+    for (; l > 0; --l) {
+      const double sc = std::fabs(h(l - 1, l - 1)) + std::fabs(h(l, l));
+      if (std::fabs(h(l, l - 1)) <= 1e-15 * (sc > 0 ? sc : 1.0)) {
+        h(l, l - 1) = 0.0;
+        break;
+      }
+    }
+    if (l == hi) {  // one real eigenvalue
+      w[hi] = h(hi, hi);
+      --hi;
+      its = 0;
+      continue;
+    }
+    if (l == hi - 1) {  // a 2 x 2 block
+      const double a = h(hi - 1, hi - 1), b = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
+      const double tr = 0.5 * (a + d), det = a * d - b * c, disc = tr * tr - det;
+      if (disc >= 0) {
+        const double r = std::sqrt(disc), e1 = tr + (tr >= 0 ? r : -r);
+        w[hi - 1] = e1;
+        w[hi] = e1 != 0.0 ? det / e1 : tr - (tr >= 0 ? r : -r);
+      } else {
+        const double r = std::sqrt(-disc);
+        w[hi - 1] = cplx(tr, r);
+        w[hi] = cplx(tr, -r);
+      }
+      hi -= 2;
+      its = 0;
+      continue;
+    }
+    if (++its > 60) return false;
+    // double shift from the trailing 2 x 2 block (exceptional shifts after
+    // 10 and 20 steps without deflation)
+    double s = h(hi - 1, hi - 1) + h(hi, hi);
+    double t = h(hi - 1, hi - 1) * h(hi, hi) - h(hi - 1, hi) * h(hi, hi - 1);
+    if (its == 10 || its == 20) {
+      const double e = std::fabs(h(hi, hi - 1)) + std::fabs(h(hi - 1, hi - 2));
+      s = 1.5 * e;
+      t = e * e;
+    }
+    double x[3] = {h(l, l) * h(l, l) + h(l, l + 1) * h(l + 1, l) - s * h(l, l) + t,
+                   h(l + 1, l) * (h(l, l) + h(l + 1, l + 1) - s), h(l + 1, l) * h(l + 2, l + 1)};
+    for (int k = l; k <= hi - 2; ++k) {
+      double v[3];
+      house(x, 3, v);
+      const int c0 = k > l ? k - 1 : l;
+      reflect(v, 3, k, c0, hi, l, std::min(k + 3, hi));
+      x[0] = h(k + 1, k);
+      x[1] = h(k + 2, k);
+      if (k < hi - 2) x[2] = h(k + 3, k);
+    }
+    double v[3];
+    house(x, 2, v);
+    reflect(v, 2, hi - 1, hi - 2, hi, l, hi);
   }
   return true;
 }
