@@ -98,10 +98,12 @@ def calibration_copy(dev):
 
 def learned_main(args):
     """Learned initial guesses on the trajectory family H(x) = H0 + sum_k x_k H_k:
-    solve the training geometries, fit PCA bases of the amplitudes and of the
-    excited-state vectors on the device, train the perceptron on the device,
-    then time held-out geometries with the plain start and with the predicted
-    start (every prediction judged by the solvers' residuals)."""
+    solve the training geometries (energies, gradients and couplings of every
+    target, collecting amplitudes, right vectors, zeta and the multipliers of
+    every target), fit PCA bases of each family on the device, train the
+    perceptron on the device, then solve held-out geometries from the plain
+    start and from the predicted start (every prediction judged by the
+    solvers' residuals, with the plain start as fallback)."""
     import numpy as np
     import torch
     from paper_2403_01007_amd import Context
@@ -110,72 +112,81 @@ def learned_main(args):
 
     S = make_system(args.learned_workload)
     dev = torch.device("cuda:0")
-    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11)
+    mk = lambda tol: Context(S.o, S.v, S.nj, S.nstates, tol=tol, tol_overlap=0.1 * tol)
     ns, npair = S.nstates, S.nstates * (S.nstates - 1) // 2
+    states, pairs = list(range(ns)), list(S.nacs)
+    nt = len(states) + len(pairs)
+    dh = torch.as_tensor(S.dh, device=dev)
+    dL = torch.as_tensor(S.dL, device=dev)
 
-    def solve(x, guess=None):
-        nonlocal ctx
+    def solve(ctx, x, guess=None, keep=False):
         h, L = S.at(x)
         ctx.set_hamiltonian_fixed_basis(torch.as_tensor(h, device=dev), torch.as_tensor(L, device=dev))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        it_g = 0
-        fb = 0
+        it_g, fb = 0, 0
         if guess is not None:
-            tg, rg = guess
-            _, info = ctx.ground(tg)
+            _, info = ctx.ground(guess["t"])
             it_g, fb = info.iterations, info.fallback_used
-        E, z, info = ctx.excited(None if guess is None else rg)
-        t_exc = time.perf_counter() - t0
-        for n in range(ns):
-            ctx.gradient(n, dh, dL)
-        for (m, n) in S.nacs:
-            ctx.nac(m, n, dh, dL)
+        E, z, info = ctx.excited(None if guess is None else guess["r"])
+        it_e, fb = info.iterations + it_g, fb or info.fallback_used
         torch.cuda.synchronize()
-        return dict(E=np.asarray(E), zeta=np.asarray(z), t_exc=t_exc, t_all=time.perf_counter() - t0,
-                    iters=info.iterations + it_g, fallback=fb or info.fallback_used)
+        t_exc = time.perf_counter() - t0
+        res = ctx.gradients_and_couplings(states, pairs, dh, dL, guess=None if guess is None else guess["m"],
+                                          multipliers=keep)
+        g, d, info = res[:3]
+        torch.cuda.synchronize()
+        out = dict(E=np.asarray(E), zeta=np.asarray(z), g=g, d=d, t_exc=t_exc, t_all=time.perf_counter() - t0,
+                   it_exc=it_e, it_mult=info.iterations, fallback=fb or info.fallback_used)
+        if keep:
+            out["M"] = res[3]
+        return out
 
-    dh = torch.as_tensor(S.dh, device=dev)
-    dL = torch.as_tensor(S.dL, device=dev)
+    # training geometries at the training tolerance; those that do not
+    # converge from the plain start are left out (and counted)
     Xtr = family_geometries(S.ncoord, range(10000, 10000 + args.ntrain))
     Xte = family_geometries(S.ncoord, range(20000, 20000 + args.nheld))
     nst = 1 + S.o * S.v * (1 + S.o * S.v)
+    ctx = mk(args.train_tol)
+    nm = ctx.multiplier_length()
     Tm = torch.empty((args.ntrain, nst - 1), dtype=torch.float64, device=dev)
     Rm = torch.empty((args.ntrain, ns * nst), dtype=torch.float64, device=dev)
+    Mm = torch.empty((args.ntrain, nt * nm), dtype=torch.float64, device=dev)
     Zm = np.zeros((args.ntrain, npair))
-    def fresh_context():
-        nonlocal ctx
-        ctx.close()
-        ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11)
-
-    # geometries whose solve does not converge from the plain start are left
-    # out (and counted); the context is rebuilt after each such failure
     t0 = time.perf_counter()
     used, skipped_train = [], 0
     for i, x in enumerate(Xtr):
         try:
-            r = solve(x)
+            r = solve(ctx, x, keep=True)
         except SccError as e:
             skipped_train += 1
             print(f"[learned: training geometry {i} skipped: {e}]", file=sys.stderr, flush=True)
-            fresh_context()
+            ctx.close()
+            ctx = mk(args.train_tol)
             continue
         q = len(used)
         Tm[q] = ctx.get(FIELD_T)
         for k in range(ns):
             Rm[q, k * nst:(k + 1) * nst] = ctx.get(FIELD_R, k)
+        Mm[q] = r["M"].reshape(-1)
         Zm[q] = r["zeta"]
         used.append(i)
-        if (i + 1) % 20 == 0:
-            print(f"[learned: {i + 1} training geometries done]", file=sys.stderr, flush=True)
+        print(f"[learned: training geometry {i} done ({r['t_all']:.1f} s)]", file=sys.stderr, flush=True)
+    ctx.close()
     ntr = len(used)
-    Xtr, Tm, Rm, Zm = Xtr[used], Tm[:ntr], Rm[:ntr], Zm[:ntr]
+    Xtr, Tm, Rm, Mm, Zm = Xtr[used], Tm[:ntr], Rm[:ntr], Mm[:ntr], Zm[:ntr]
     t_data = time.perf_counter() - t0
-    print(f"[learned: {args.ntrain} training geometries solved in {t_data:.1f} s]", file=sys.stderr, flush=True)
     kt = min(64, ntr - 1)
     mt, Ut, Ct, _ = pca_fit(Tm, kt)
     mr, Ur, Cr, _ = pca_fit(Rm, kt)
-    Y = np.concatenate([Ct.cpu().numpy(), Cr.cpu().numpy(), Zm], axis=1)
+    mm, Um, Cm, _ = pca_fit(Mm, kt)
+    del Tm, Rm, Mm
+    Y = np.concatenate([Ct.cpu().numpy(), Cr.cpu().numpy(), Cm.cpu().numpy(), Zm], axis=1)
+    # the network learns standardised outputs (every PCA coefficient and zeta
+    # with zero mean and unit spread over the training set)
+    ymu, ysd = Y.mean(axis=0), Y.std(axis=0) + 1e-12
+    Y = (Y - ymu) / ysd
+    ymu_d, ysd_d = torch.as_tensor(ymu, device=dev), torch.as_tensor(ysd, device=dev)
     nout = Y.shape[1]
     rng = np.random.Generator(np.random.PCG64(4242))
     nh = 256
@@ -189,59 +200,64 @@ def learned_main(args):
     losses = net.train(Xtr, Y, order, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    print(f"[learned: trained {args.train_steps} steps in {t_train:.2f} s, loss {losses[0]:.3e} -> "
-          f"{losses[-20:].mean():.3e}]", file=sys.stderr, flush=True)
-    plain, learned, held = [], [], []
+    print(f"[learned: {ntr} training geometries in {t_data:.1f} s; trained {args.train_steps} steps in "
+          f"{t_train:.2f} s, loss {losses[0]:.3e} -> {losses[-20:].mean():.3e}]", file=sys.stderr, flush=True)
+    # held-out geometries at the benchmark tolerance: plain start on a fresh
+    # context each, learned start on one context along the held-out sequence
+    plain, learned = [], []
+    lctx = mk(1e-10)
+    failed = 0
     for i, x in enumerate(Xte):
+        pctx = mk(1e-10)
         try:
-            plain.append(solve(x))
-            held.append(i)
+            rp = solve(pctx, x)
         except SccError as e:
             print(f"[learned: held-out geometry {i} skipped (plain start): {e}]", file=sys.stderr, flush=True)
-            fresh_context()
-    print(f"[learned: {len(held)} held-out geometries solved from the plain start]", file=sys.stderr, flush=True)
-    # a fresh context for the learned starts: each held-out geometry inherits
-    # only what the previous learned solve left (as along a trajectory)
-    ctx.close()
-    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-10, tol_overlap=1e-11)
-    failed_learned = 0
-    kept_plain = []
-    for i, x in zip(held, Xte[held]):
+            pctx.close()
+            continue
+        pctx.close()
         c0 = time.perf_counter()
-        yp = net.forward(x[None, :]).to(torch.float64)
-        tg = pca_expand(mt, Ut, yp[:, :kt])[0]
-        rg = pca_expand(mr, Ur, yp[:, kt:2 * kt])[0]
-        guess_r = torch.cat([rg, yp[0, 2 * kt:]])
+        yp = net.forward(x[None, :]).to(torch.float64) * ysd_d + ymu_d
+        guess = {"t": pca_expand(mt, Ut, yp[:, :kt])[0],
+                 "r": torch.cat([pca_expand(mr, Ur, yp[:, kt:2 * kt])[0], yp[0, 3 * kt:]]),
+                 "m": pca_expand(mm, Um, yp[:, 2 * kt:3 * kt])[0].reshape(nt, nm)}
+        torch.cuda.synchronize()
         t_pred = time.perf_counter() - c0
         try:
-            r = solve(x, (tg, guess_r))
+            rl = solve(lctx, x, guess)
         except SccError as e:
-            failed_learned += 1
+            failed += 1
             print(f"[learned: held-out geometry {i} failed from the learned start: {e}]", file=sys.stderr, flush=True)
-            fresh_context()
+            lctx.close()
+            lctx = mk(1e-10)
             continue
-        r["t_exc"] += t_pred
-        r["t_all"] += t_pred
-        learned.append(r)
-        kept_plain.append(plain[held.index(i)])
-    plain = kept_plain
-    dE = max(float(np.abs(a["E"] - b["E"]).max()) for a, b in zip(plain, learned))
+        rl["t_exc"] += t_pred
+        rl["t_all"] += t_pred
+        plain.append(rp)
+        learned.append(rl)
+        print(f"[learned: held-out {i}: plain {rp['t_all']:.1f} s ({rp['it_exc']}+{rp['it_mult']} it), learned "
+              f"{rl['t_all']:.1f} s ({rl['it_exc']}+{rl['it_mult']} it)]", file=sys.stderr, flush=True)
     mean = lambda rs, key: float(np.mean([r[key] for r in rs]))
+    diff = lambda key: max(float(np.abs(np.asarray(a[key]) - np.asarray(b[key])).max()) for a, b in zip(plain, learned))
     line = {
         "metric": "s/geometry (energies+gradients+NACs), MFMA TFLOP/s; mixed+learned vs FP64",
-        "value": mean(learned, "t_all"), "unit": "s/geometry", "n_gpus": 1, "steps": args.nheld, "warmup": 0,
+        "value": mean(learned, "t_all"), "unit": "s/geometry", "n_gpus": 1, "steps": len(learned), "warmup": 0,
         "ms_per_step": 1e3 * mean(learned, "t_all"), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.learned_workload, "guess": "learned", "ntrain": ntr,
-                   "nheld": len(learned), "pca": kt, "mlp": [S.ncoord, nh, nh, nout],
-                   "skipped_training": skipped_train, "skipped_held_out": args.nheld - len(held),
-                   "failed_learned": failed_learned},
+                   "train_tol": args.train_tol, "nheld": len(learned), "pca": kt, "mlp": [S.ncoord, nh, nh, nout],
+                   "skipped_training": skipped_train, "failed_learned": failed},
         "learned": {"plain_s_per_geometry": mean(plain, "t_all"), "learned_s_per_geometry": mean(learned, "t_all"),
+                    "speedup": mean(plain, "t_all") / mean(learned, "t_all"),
                     "plain_excited_s": mean(plain, "t_exc"), "learned_excited_s": mean(learned, "t_exc"),
-                    "plain_iterations": mean(plain, "iters"), "learned_iterations": mean(learned, "iters"),
-                    "fallbacks": int(sum(r["fallback"] for r in learned)), "max_abs_energy_diff": dE,
-                    "training_data_s": t_data, "training_s": t_train,
-                    "final_loss": float(losses[-20:].mean())},
+                    "plain_iterations_excited": mean(plain, "it_exc"),
+                    "learned_iterations_excited": mean(learned, "it_exc"),
+                    "plain_iterations_multipliers": mean(plain, "it_mult"),
+                    "learned_iterations_multipliers": mean(learned, "it_mult"),
+                    "fallbacks": int(sum(r["fallback"] for r in learned)),
+                    "max_abs_diff_energy": diff("E"), "max_abs_diff_gradient": diff("g"),
+                    "max_abs_diff_coupling": diff("d"),
+                    "training_data_s": t_data, "training_s": t_train, "final_loss": float(losses[-20:].mean())},
     }
     print(json.dumps(line), flush=True)
 
@@ -277,6 +293,8 @@ def main():
     ap.add_argument("--ntrain", type=int, default=200)
     ap.add_argument("--nheld", type=int, default=20)
     ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-tol", type=float, default=1e-8,
+                    help="residual tolerance of the training solves (the held-out solves use 1e-10)")
     ap.add_argument("--calibration-only", action="store_true",
                     help="only the 512 MiB device copy that scales HBM traffic counters, then exit")
     args = ap.parse_args()

@@ -213,9 +213,29 @@ int scc_nac(scc_ctx* ctx, int m, int n, int ncoord, const double* dh, const doub
  * serves all of them; each target keeps its own Krylov recurrence.
  * states: host int[ngrad]; pairs: host int[2 * npair] as (m, n);
  * grads: device double[ngrad][ncoord]; nacs: device double[npair][ncoord].
- * The multiplier equations are solved in FP64 in every precision mode. */
+ * Targets are ordered gradients first, then couplings.
+ * guess: NULL or device double[ngrad + npair][scc_multiplier_length]
+ * starting multipliers (e.g. predicted by the learned model); each is used
+ * only if its residual is below that of the zero start, else it is dropped
+ * and info->fallback_used = 1.  multipliers: NULL or device
+ * double[ngrad + npair][scc_multiplier_length], receives the converged
+ * multipliers.  The multiplier equations are solved in FP64 in every
+ * precision mode. */
 int scc_gradients_and_couplings(scc_ctx* ctx, int ngrad, const int* states, int npair, const int* pairs, int ncoord,
-                                const double* dh, const double* dchol, double* grads, double* nacs, scc_info* info);
+                                const double* dh, const double* dchol, const double* guess, double* multipliers,
+                                double* grads, double* nacs, scc_info* info);
+
+/* Length of one target's multiplier vector (host out).  Layout, row-major
+ * FP64, doubles blocks in the full symmetric [a][i][b][j] layout:
+ *   [ zeta-bar: singles (v*o) | doubles (v*o*v*o)       multipliers of Omega
+ *   | for each state k: L0-bar^k (1) | L-bar^k singles | L-bar^k doubles
+ *   |                   E-bar_k (1)                     multipliers of the
+ *                                                        eigenvalue equations
+ *                                                        and normalisation
+ *   | gamma-bar_kl for pairs k < l (row-major) ]        orthogonality
+ * (eqs. Lagrangian_gradient, Lagrangian_coupling); zero in the gamma-bar
+ * slots when the SCC constraint is inactive. */
+int scc_multiplier_length(const scc_dims* dims, long long* n);
 
 /* Export solution fields to device buffers:
  *   SCC_FIELD_T      [t1 | t2]

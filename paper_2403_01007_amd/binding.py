@@ -18,7 +18,8 @@ GEMM_KERNEL_NAMES = ["gemm_f64_kernel", "gemm_f64_two_kernel", "gemm_f32acc_kern
 
 EXPORTED_SYMBOLS = ["scc_workspace_bytes", "scc_create", "scc_destroy", "scc_last_error",
                     "scc_set_hamiltonian", "scc_set_hamiltonian_fixed_basis", "scc_ground", "scc_excited", "scc_multipliers",
-                    "scc_densities", "scc_gradient", "scc_nac", "scc_gradients_and_couplings", "scc_get", "scc_eval_residual",
+                    "scc_densities", "scc_gradient", "scc_nac", "scc_gradients_and_couplings", "scc_multiplier_length",
+                    "scc_get", "scc_eval_residual",
                     "scc_eval_sigma", "scc_eval_left", "scc_profile", "scc_profile_kernels",
                     "scc_mlp_param_count", "scc_mlp_workspace_bytes", "scc_mlp_forward", "scc_mlp_forward_noalloc",
                     "scc_mlp_loss_grad",
@@ -81,7 +82,8 @@ def load_library():
     lib.scc_gradient.argtypes = [P, I, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_nac.argtypes = [P, I, I, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_get.argtypes = [P, I, I, P]
-    lib.scc_gradients_and_couplings.argtypes = [P, I, P, I, P, I, P, P, P, P, ctypes.POINTER(Info)]
+    lib.scc_gradients_and_couplings.argtypes = [P, I, P, I, P, I, P, P, P, P, P, P, ctypes.POINTER(Info)]
+    lib.scc_multiplier_length.argtypes = [ctypes.POINTER(Dims), ctypes.POINTER(ctypes.c_longlong)]
     lib.scc_eval_residual.argtypes = [P, P, P, P, P]
     lib.scc_eval_sigma.argtypes = [P, P, P]
     lib.scc_eval_left.argtypes = [P, P, P]
@@ -241,8 +243,15 @@ class Context:
                                      ctypes.byref(info)), "scc_nac")
         return out.cpu().numpy(), info
 
-    def gradients_and_couplings(self, states, pairs, dh, dchol):
-        """All requested gradients and couplings in one call; returns (grads, nacs) host arrays."""
+    def multiplier_length(self):
+        n = ctypes.c_longlong(0)
+        self._check(self.lib.scc_multiplier_length(ctypes.byref(self.dims), ctypes.byref(n)), "scc_multiplier_length")
+        return n.value
+
+    def gradients_and_couplings(self, states, pairs, dh, dchol, guess=None, multipliers=False):
+        """All requested gradients and couplings in one call; returns (grads, nacs, info) host arrays, plus
+        the converged multipliers (device [ntarget][multiplier_length]) when multipliers=True.  guess:
+        starting multipliers of the same shape (each judged by its residual)."""
         dh, dl = self._dev(dh), self._dev(dchol)
         nc = dh.shape[0]
         st = (ctypes.c_int * max(1, len(states)))(*states)
@@ -250,12 +259,17 @@ class Context:
         pr = (ctypes.c_int * max(1, len(flat)))(*flat)
         g = self.zeros(max(1, len(states)), nc)
         d = self.zeros(max(1, len(pairs)), nc)
+        nt = len(states) + len(pairs)
+        gs = None if guess is None else self._dev(guess)
+        mo = self.zeros(nt, self.multiplier_length()) if multipliers else None
         info = Info()
         self._check(self.lib.scc_gradients_and_couplings(self.h, len(states), ctypes.cast(st, ctypes.c_void_p),
                                                          len(pairs), ctypes.cast(pr, ctypes.c_void_p), nc, _ptr(dh),
-                                                         _ptr(dl), _ptr(g), _ptr(d), ctypes.byref(info)),
+                                                         _ptr(dl), _ptr(gs), _ptr(mo), _ptr(g), _ptr(d),
+                                                         ctypes.byref(info)),
                     "scc_gradients_and_couplings")
-        return g.cpu().numpy()[:len(states)], d.cpu().numpy()[:len(pairs)], info
+        out = (g.cpu().numpy()[:len(states)], d.cpu().numpy()[:len(pairs)], info)
+        return out + (mo,) if multipliers else out
 
     def get(self, field, k=0):
         nvt = self.nov + self.nov * self.nov

@@ -146,8 +146,9 @@ struct scc_ctx {
   double* kbar = nullptr;
   double* dsc = nullptr;      // device scalars
   // singles preconditioner: eigenvectors U [nov][nov] and eigenvalues w
-  // [nov] of the singlet singles matrix of the current geometry (its A is
-  // overwritten by the eigensolver), orbital energies on the device
+  // [nov] of the singlet singles matrix of the current geometry; once
+  // diagonalised, the matrix's storage holds U^T; orbital energies on the
+  // device
   double* cisA = nullptr;
   double* cisU = nullptr;
   double* cisW = nullptr;
@@ -156,7 +157,7 @@ struct scc_ctx {
   double* cis_tmp = nullptr;
   // y = U diag(1 / floor(w - shift)) U^T x on the singles block
   void singles_solve(const double* x, double shift, double fl, double* y) {
-    launch_eig_shift_solve(cisU, cisW, (int)sz.nov, shift, fl, x, y, cis_tmp, s);
+    launch_eig_shift_solve(cisU, cisA, cisW, (int)sz.nov, shift, fl, x, y, cis_tmp, s);
   }
   Recycler rec_lag, rec_k;    // recycled Krylov spaces of the multiplier solves
   std::vector<double> eps;
@@ -1517,7 +1518,11 @@ int orbital_response(scc_ctx* c, const std::vector<Seg>& segs, const std::vector
   return SCC_OK;
 }
 
-int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
+// One target's multipliers.  guess (device, [nlag], may be NULL) is used as
+// the starting point if its residual is below that of the zero start (else
+// *rejected = true); xout (device, may be NULL) receives the multipliers.
+int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info, const double* guess = nullptr,
+                      double* xout = nullptr, bool* rejected = nullptr) {
   Model& m = c->m;
   const int64_t n = c->sz.nlag;
   set_lagrangian_point(c);
@@ -1544,8 +1549,25 @@ int multipliers_solve(scc_ctx* c, int kind, int mm, int nn, scc_info* info) {
   // with FP32 products the Krylov recurrence of this bordered system drifts
   // away from its true residual (directions of large norm amplify the
   // product rounding), so a reduced-precision pass is no usable start.
-  rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, iters, rel);
+  bool warm = false;
+  if (guess) {
+    PoolMark pg(c);
+    double* r = c->alloc(n);
+    c->cp(x, guess, n);
+    apply(x, r);
+    c->axpby(1.0, b, -1.0, r, n);
+    DotBatch db;
+    const int ir = db.dot(r, r), ib = db.dot(b, b);
+    const auto res = db.run(c, n);
+    warm = std::isfinite(res[ir][0]) && res[ir][0] < res[ib][0];
+    if (!warm) {
+      c->fill(x, n, 0.0);
+      if (rejected) *rejected = true;
+    }
+  }
+  rc = gcr(c, c->rec_lag, apply, prec, b, x, c->opt.tol_residual, maxg, iters, rel, warm);
   if (rc) return rc;
+  if (xout) c->cp(xout, x, n);
   int itk = 0;
   double relk = 0;
   rc = orbital_response(c, segs, offs, x, kind, mm, nn, itk, relk);
@@ -1596,7 +1618,7 @@ struct Target {
 // per target.  Targets that do not converge within the batched capacity are
 // solved alone.
 int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const double* dh, const double* dchol,
-                  int& iters_total) {
+                  int& iters_total, const double* guess, double* mult, bool& rejected) {
   Model& m = c->m;
   const int64_t n = c->sz.nlag, un = up(c->sz.nlag);
   const int nbt = c->sz.nbt, cap = c->sz.cap_b;
@@ -1667,6 +1689,36 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
       c->cp(R[j], B[j], n);
       bn[j] = std::sqrt(c->dot(B[j], B[j], n));
       if (bn[j] == 0) done[j] = 1;
+    }
+    if (guess) {
+      // starting points judged by their residuals: b - J^T x0 for all targets
+      // with one batched product; a guess no better than zero is dropped
+      std::vector<const double*> gin(nb);
+      std::vector<double*> gout(nb);
+      for (int j = 0; j < nb; ++j) {
+        c->cp(X[j], guess + (int64_t)(b0 + j) * n, n);
+        gin[j] = X[j];
+        gout[j] = W[j];
+      }
+      applyB(gin, gout);
+      DotBatch db;
+      std::vector<int> ir(nb);
+      for (int j = 0; j < nb; ++j) {
+        c->cp(Z[j], B[j], n);
+        c->axpby(-1.0, W[j], 1.0, Z[j], n);
+        ir[j] = db.dot(Z[j], Z[j]);
+      }
+      const auto res = db.run(c, n);
+      for (int j = 0; j < nb; ++j) {
+        const double rn = std::sqrt(res[ir[j]][0]);
+        if (std::isfinite(rn) && rn < bn[j]) {
+          c->cp(R[j], Z[j], n);
+          if (bn[j] > 0 && rn < tol * bn[j]) force[j] = 1;  // confirm on the true residual at once
+        } else {
+          c->fill(X[j], n, 0.0);
+          rejected = true;
+        }
+      }
     }
     int it = 0;
     for (; it < maxg; ++it) {
@@ -1805,6 +1857,7 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
         failed.push_back((int)(b0 + j));
         continue;
       }
+      if (mult) c->cp(mult + (int64_t)(b0 + j) * n, X[j], n);
       int itk = 0;
       double relk = 0;
       int rc = orbital_response(c, segs, offs, X[j], t.kind, t.m, t.n, itk, relk);
@@ -1818,7 +1871,8 @@ int targets_solve(scc_ctx* c, const std::vector<Target>& tg, int ncoord, const d
     const Target& t = tg[f];
     c->log("  target %d solved alone\n", f);
     scc_info inf{};
-    int rc = multipliers_solve(c, t.kind, t.m, t.n, &inf);
+    int rc = multipliers_solve(c, t.kind, t.m, t.n, &inf, guess ? guess + (int64_t)f * n : nullptr,
+                               mult ? mult + (int64_t)f * n : nullptr, &rejected);
     if (rc) return rc;
     iters_total += inf.iterations;
     contract_derivatives(c, ncoord, dh, dchol, t.out);
@@ -1920,6 +1974,13 @@ int install_mo_hamiltonian(scc_ctx* c, double e_nuc) { return install_mo_hamilto
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
+
+int scc_multiplier_length(const scc_dims* dims, long long* n) {
+  if (!valid_dims(dims) || !n) return SCC_EINVAL;
+  const long long nov = (long long)dims->nocc * dims->nvirt, ns = dims->nstates;
+  *n = nov + nov * nov + ns * (2 + nov + nov * nov) + ns * (ns - 1) / 2;
+  return SCC_OK;
+}
 
 int scc_workspace_bytes(const scc_dims* dims, const scc_options* opts, size_t* bytes) {
   (void)opts;
@@ -2199,6 +2260,7 @@ int install_mo_hamiltonian_impl(scc_ctx* c, double e_nuc) {
     c->xfer(c->eps_d, c->eps.data(), N * sizeof(double), hipMemcpyHostToDevice);
     launch_cis_matrix(c->tp(m.L), J, o, v, c->eps_d, c->cisA, c->s);
     const int sweeps = sym_eig_jacobi(c->cisA, c->cisU, c->cisW, (int)nov, c->cis_work, c->s);
+    launch_transpose(c->cisU, (int)nov, c->cisA, c->s);
     c->log(" singles matrix diagonalised in %d Jacobi sweeps\n", sweeps);
     // every geometry starts cold: t = 0 (the first Jacobi step is MP2), zeta = 0
     c->fill(c->tp(m.t1), nov, 0.0);
@@ -2406,7 +2468,8 @@ int scc_nac(scc_ctx* c, int m, int n, int ncoord, const double* dh, const double
 }
 
 int scc_gradients_and_couplings(scc_ctx* c, int ngrad, const int* states, int npair, const int* pairs, int ncoord,
-                                const double* dh, const double* dchol, double* grads, double* nacs, scc_info* info) {
+                                const double* dh, const double* dchol, const double* guess, double* multipliers,
+                                double* grads, double* nacs, scc_info* info) {
   if (!c) return SCC_EINVAL;
   const int ns = c->m.d.ns;
   if (ngrad < 0 || npair < 0 || (ngrad > 0 && (!states || !grads)) || (npair > 0 && (!pairs || !nacs)) || !dh ||
@@ -2436,12 +2499,17 @@ int scc_gradients_and_couplings(scc_ctx* c, int ngrad, const int* states, int np
   }
   return guarded(c, info, [&]() -> int {
     int iters = 0;
-    int rc = c->m.nbt > 1 ? targets_solve(c, tg, ncoord, dh, dchol, iters) : SCC_EINVAL;
-    if (c->m.nbt <= 1) {
-      rc = SCC_OK;
-      for (auto& t : tg) {
+    bool rejected = false;
+    int rc = SCC_OK;
+    if (c->m.nbt > 1) {
+      rc = targets_solve(c, tg, ncoord, dh, dchol, iters, guess, multipliers, rejected);
+    } else {
+      const int64_t n = c->sz.nlag;
+      for (size_t i = 0; i < tg.size(); ++i) {
+        const Target& t = tg[i];
         scc_info inf{};
-        rc = multipliers_solve(c, t.kind, t.m, t.n, &inf);
+        rc = multipliers_solve(c, t.kind, t.m, t.n, &inf, guess ? guess + (int64_t)i * n : nullptr,
+                               multipliers ? multipliers + (int64_t)i * n : nullptr, &rejected);
         if (rc) break;
         iters += inf.iterations;
         contract_derivatives(c, ncoord, dh, dchol, t.out);
@@ -2450,6 +2518,7 @@ int scc_gradients_and_couplings(scc_ctx* c, int ngrad, const int* states, int np
     if (info) {
       info->iterations = iters;
       info->converged = rc == SCC_OK;
+      info->fallback_used = rejected ? 1 : 0;
     }
     return rc;
   });

@@ -169,17 +169,39 @@ __global__ void diag_kernel(const double* __restrict__ A, int n, double* w) {
   if (i < n) w[i] = A[(int64_t)i * n + i];
 }
 
-// u_k = (sum_i U[i][k] x_i) / floor(w_k - shift), one thread per k
-__global__ __launch_bounds__(256) void eig_proj_kernel(const double* __restrict__ U, const double* __restrict__ w,
+// u_k = (sum_i UT[k][i] x_i) / floor(w_k - shift) with UT = U^T, one wave
+// per k (rows of UT are contiguous)
+__global__ __launch_bounds__(256) void eig_proj_kernel(const double* __restrict__ UT, const double* __restrict__ w,
                                                        int n, double shift, double fl, const double* __restrict__ x,
                                                        double* __restrict__ u) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + wave;
+  if (k >= n) return;  // the whole wave leaves together (no barriers below)
+  const double* row = UT + (int64_t)k * n;
   double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += U[(int64_t)i * n + k] * x[i];
-  double d = w[k] - shift;
-  if (fabs(d) < fl) d = d < 0.0 ? -fl : fl;
-  u[k] = acc / d;
+  for (int i = lane; i < n; i += 64) acc += row[i] * x[i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    double d = w[k] - shift;
+    if (fabs(d) < fl) d = d < 0.0 ? -fl : fl;
+    u[k] = acc / d;
+  }
+}
+
+// UT = U^T (32 x 32 tiles through LDS)
+__global__ void transpose_kernel(const double* __restrict__ U, int n, double* __restrict__ UT) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int i = by + r, j = bx + tx;
+    if (i < n && j < n) tile[r][tx] = U[(int64_t)i * n + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bx + r, j = by + tx;
+    if (i < n && j < n) UT[(int64_t)i * n + j] = tile[tx][r];
+  }
 }
 
 // y_i = sum_k U[i][k] u_k, one wave per row
@@ -267,9 +289,15 @@ void launch_eig_column(const double* U, int n, int k, double* y, hipStream_t s) 
   hck(hipGetLastError(), "eigenvector column");
 }
 
-void launch_eig_shift_solve(const double* U, const double* w, int n, double shift, double fl, const double* x,
-                            double* y, double* tmp, hipStream_t s) {
-  hipLaunchKernelGGL(eig_proj_kernel, dim3(blocks(n)), dim3(256), 0, s, U, w, n, shift, fl, x, tmp);
+void launch_transpose(const double* U, int n, double* UT, hipStream_t s) {
+  dim3 grid((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32));
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, U, n, UT);
+  hck(hipGetLastError(), "transpose");
+}
+
+void launch_eig_shift_solve(const double* U, const double* UT, const double* w, int n, double shift, double fl,
+                            const double* x, double* y, double* tmp, hipStream_t s) {
+  hipLaunchKernelGGL(eig_proj_kernel, dim3((n + 3) / 4), dim3(256), 0, s, UT, w, n, shift, fl, x, tmp);
   hipLaunchKernelGGL(eig_back_kernel, dim3((n + 3) / 4), dim3(256), 0, s, U, n, tmp, y);
   hck(hipGetLastError(), "eig shift solve");
 }

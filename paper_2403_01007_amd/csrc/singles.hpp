@@ -28,9 +28,13 @@ int sym_eig_jacobi(double* A, double* V, double* w, int n, double* work, hipStre
 // y [n] = column k of U [n][n].
 void launch_eig_column(const double* U, int n, int k, double* y, hipStream_t s);
 
+// UT [n][n] = U^T (device).
+void launch_transpose(const double* U, int n, double* UT, hipStream_t s);
+
 // y = U diag(1 / d_k) U^T x, d_k = w_k - shift floored to |d_k| >= fl (sign
-// kept); tmp [n] device scratch; y may alias x only if tmp does not.
-void launch_eig_shift_solve(const double* U, const double* w, int n, double shift, double fl, const double* x,
-                            double* y, double* tmp, hipStream_t s);
+// kept), with UT = U^T stored; tmp [n] device scratch; y may alias x only
+// if tmp does not.
+void launch_eig_shift_solve(const double* U, const double* UT, const double* w, int n, double shift, double fl,
+                            const double* x, double* y, double* tmp, hipStream_t s);
 
 }  // namespace scc

@@ -415,3 +415,33 @@ def test_o6v26_batched_targets_against_stored_oracle():
         err = np.abs(d[i] - np.asarray(ref["nac"][f"{m},{n}"])).max()
         print(f"  nac {(m, n)} max err {err:.2e}", flush=True)
         assert err < G_TOL
+
+
+def test_multiplier_guesses():
+    """Starting multipliers for the lockstep gradient/coupling solve: the
+    converged multipliers of a solve restart it in a few Krylov steps with
+    the same results; a perturbed guess takes fewer steps than the zero
+    start; a guess that is not finite is dropped (fallback_used) and changes
+    nothing."""
+    import torch
+    S = make_system("o5v19", seed=7)
+    print("[multiplier guesses o5v19]", flush=True)
+    ctx, e0, E, z, grads, nacs = _run_gpu(S)
+    pairs = list(S.nacs) + [(n, m) for (m, n) in S.nacs]
+    states = list(range(S.nstates))
+    g0, d0, info0, M = ctx.gradients_and_couplings(states, pairs, S.dh, S.dL, multipliers=True)
+    assert M.shape == (len(states) + len(pairs), ctx.multiplier_length())
+    g1, d1, info1 = ctx.gradients_and_couplings(states, pairs, S.dh, S.dL, guess=M)
+    print(f"  zero start {info0.iterations} iterations, converged guess {info1.iterations}", flush=True)
+    assert info1.fallback_used == 0 and info1.iterations < info0.iterations
+    assert np.abs(g1 - g0).max() < G_TOL and np.abs(d1 - d0).max() < G_TOL
+    noise = torch.as_tensor(np.random.default_rng(3).normal(size=tuple(M.shape)), device=M.device)
+    Mp = M + 1e-4 * M.abs().max() * noise
+    g2, d2, info2 = ctx.gradients_and_couplings(states, pairs, S.dh, S.dL, guess=Mp)
+    print(f"  perturbed guess {info2.iterations} iterations", flush=True)
+    assert info2.fallback_used == 0 and info2.iterations < info0.iterations
+    assert np.abs(g2 - g0).max() < G_TOL and np.abs(d2 - d0).max() < G_TOL
+    bad = torch.full_like(M, float("nan"))
+    g3, d3, info3 = ctx.gradients_and_couplings(states, pairs, S.dh, S.dL, guess=bad)
+    assert info3.fallback_used == 1
+    assert np.abs(g3 - g0).max() < G_TOL and np.abs(d3 - d0).max() < G_TOL
