@@ -971,6 +971,39 @@ void launch_deriv_contract(const double* dh, int64_t nh, const double* D1, const
 // ---------------------------------------------------------------------------
 // planning
 // ---------------------------------------------------------------------------
+// Split-K plan of one unbatched GEMM with `tiles` output tiles and summed
+// length K.  The grid holds tiles * sp workgroups, of which GEMM_SLOTS are
+// resident at once (256 CUs, four 256-thread workgroups each); the time is
+// modelled as (rounds of resident workgroups) x (one workgroup's K chunk)
+// plus the partial sums written and read back by the reduction.  A grid just
+// above a multiple of the resident slots runs a nearly empty last round, so
+// the split is chosen to fill the rounds, not only to reach one full round.
+// The partial buffer is capped at 64 Mi doubles.  Returns sp (1: no split).
+constexpr int64_t GEMM_SLOTS = 1024;
+static int64_t choose_splits(int64_t M, int64_t N, int64_t K, int64_t tiles, int64_t& kchunk) {
+  kchunk = K;
+  if (K < 128 || M <= 0 || N <= 0) return 1;
+  const double slot_rate = 45e12 / GEMM_SLOTS;  // FP64 flop/s of one resident workgroup
+  const double red_rate = 5e12;                 // bytes/s of the partial-sum traffic
+  const int64_t spmax = std::min<int64_t>({K / 64, (int64_t)1024, std::max<int64_t>(1, (64ll << 20) / (M * N))});
+  double best = 0;
+  int64_t bsp = 1;
+  for (int64_t sp = 1; sp <= spmax; ++sp) {
+    int64_t kc = (K + sp - 1) / sp;
+    kc = (kc + BK - 1) / BK * BK;
+    if ((K + kc - 1) / kc != sp) continue;
+    const int64_t rounds = (tiles * sp + GEMM_SLOTS - 1) / GEMM_SLOTS;
+    double t = (double)rounds * 2.0 * BM * BN * (double)kc / slot_rate;
+    if (sp > 1) t += (double)(sp + 1) * (double)M * (double)N * 8.0 / red_rate;
+    if (sp == 1 || t < 0.97 * best) {
+      best = t;
+      bsp = sp;
+      kchunk = kc;
+    }
+  }
+  return bsp;
+}
+
 static std::vector<int64_t> row_major_strides(const TensorDesc& d) {
   std::vector<int64_t> s(d.nd, 1);
   for (int i = d.nd - 2; i >= 0; --i) s[i] = s[i + 1] * d.dim[i + 1];
@@ -1257,24 +1290,16 @@ static ContractPlan plan_multi(const Graph& g, const Op& op, double* arena, doub
   for (GemmSeg& q : P.segs)
     for (IdxMap* m : {&q.mAm, &q.mAk, &q.mBk, &q.mBn})
       if (m->D == 0) *m = ident;
-  // split-K over the concatenated summed index when the tiles cannot fill the chip
-  {
-    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * Bt;
-    const int64_t target = 1024;
-    if (Bt == 1 && ktot >= 128 && tiles < target) {
-      int64_t sp = std::min<int64_t>((target + tiles - 1) / tiles, ktot / 64);
-      sp = std::min<int64_t>(sp, 1024);
-      if (sp > 1) {
-        int64_t kc = (ktot + sp - 1) / sp;
-        kc = (kc + BK - 1) / BK * BK;
-        sp = (ktot + kc - 1) / kc;
-        if (sp > 1) {
-          G.splits = sp;
-          G.kchunk = kc;
-          G.P = scratch + sc;
-          sc += sp * M * N;
-        }
-      }
+  // split-K over the concatenated summed index (fills the resident slots)
+  if (Bt == 1) {
+    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    int64_t kc = 0;
+    const int64_t sp = choose_splits(M, N, ktot, tiles, kc);
+    if (sp > 1) {
+      G.splits = sp;
+      G.kchunk = kc;
+      G.P = scratch + sc;
+      sc += sp * M * N;
     }
   }
   P.scratch = sc;
@@ -1575,24 +1600,16 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
     P.scratch = sc;
     return P;
   }
-  // split-K when the output tiles cannot fill the chip and K is long
-  {
-    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * Bt;
-    const int64_t target = 1024;
-    if (Bt == 1 && K >= 128 && tiles < target) {
-      int64_t sp = std::min<int64_t>((target + tiles - 1) / tiles, K / 64);
-      sp = std::min<int64_t>(sp, 1024);
-      if (sp > 1) {
-        int64_t kc = (K + sp - 1) / sp;
-        kc = (kc + BK - 1) / BK * BK;
-        sp = (K + kc - 1) / kc;
-        if (sp > 1) {
-          G.splits = sp;
-          G.kchunk = kc;
-          G.P = scratch + sc;
-          sc += sp * M * N;
-        }
-      }
+  // split-K (fills the resident slots; long K with few output tiles)
+  if (Bt == 1) {
+    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    int64_t kc = 0;
+    const int64_t sp = choose_splits(M, N, K, tiles, kc);
+    if (sp > 1) {
+      G.splits = sp;
+      G.kchunk = kc;
+      G.P = scratch + sc;
+      sc += sp * M * N;
     }
   }
   P.scratch = sc;
