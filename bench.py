@@ -55,8 +55,8 @@ def oracle_baseline(S, workload, iterations=25):
     workload: `iterations` steps of its own CCSD ground-state iteration (the
     residual with full N^4 integrals plus its DIIS step) at x = 0, scaled to
     one geometry by the oracle's whole-geometry time in units of the same
-    step, from its complete run at o6v26 (three states, three gradients,
-    three couplings; tests/golden/o6v26.json, written by scripts that call
+    step, from its complete run of a three-state system (three gradients,
+    three couplings; tests/golden/<name>.json, written by scripts that call
     only the oracle)."""
     import numpy as np
     import torch
@@ -64,9 +64,15 @@ def oracle_baseline(S, workload, iterations=25):
     from oracle import scc as oscc
     threads = len(os.sched_getaffinity(0))
     torch.set_num_threads(threads)
-    ref_path = os.path.join(ROOT, "tests", "golden", "o6v26.json")
-    ref = json.load(open(ref_path)).get("oracle_timing", {}) if os.path.exists(ref_path) else {}
-    if "ground_iteration_seconds" not in ref:
+    ref, ref_name = {}, None
+    for name in ("o6v26", "o4v12s3"):
+        ref_path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+        if os.path.exists(ref_path):
+            ref = json.load(open(ref_path)).get("oracle_timing", {})
+            if "ground_iteration_seconds" in ref:
+                ref_name = name
+                break
+    if ref_name is None:
         return None
     h, L = S.at(np.zeros(S.ncoord))
     ht = torch.as_tensor(h)
@@ -82,8 +88,8 @@ def oracle_baseline(S, workload, iterations=25):
     return {"value": t_step * ratio, "unit": "s/geometry", "cores": threads, "kind": "oracle",
             "sample": (f"{iterations} steps of the oracle's CCSD ground-state iteration at {workload} "
                        f"({t_step:.2f} s per step, torch CPU FP64 with N^4 integrals) times {ratio:.0f}, the "
-                       f"oracle's whole-geometry time in units of that step in its complete o6v26 run "
-                       f"(energies, 3 gradients, 3 couplings; tests/golden/o6v26.json, {ref['threads']} threads)")}
+                       f"oracle's whole-geometry time in units of that step in its complete {ref_name} run "
+                       f"(energies, 3 gradients, 3 couplings; tests/golden/{ref_name}.json, {ref['threads']} threads)")}
 
 
 def calibration_copy(dev):
@@ -162,6 +168,7 @@ def learned_main(args):
             skipped_train += 1
             print(f"[learned: training geometry {i} skipped: {e}]", file=sys.stderr, flush=True)
             ctx.close()
+            torch.cuda.empty_cache()
             ctx = mk(args.train_tol)
             continue
         q = len(used)
@@ -173,6 +180,7 @@ def learned_main(args):
         used.append(i)
         print(f"[learned: training geometry {i} done ({r['t_all']:.1f} s)]", file=sys.stderr, flush=True)
     ctx.close()
+    torch.cuda.empty_cache()  # the next contexts need the whole workspace block back
     ntr = len(used)
     Xtr, Tm, Rm, Mm, Zm = Xtr[used], Tm[:ntr], Rm[:ntr], Mm[:ntr], Zm[:ntr]
     t_data = time.perf_counter() - t0
@@ -214,8 +222,10 @@ def learned_main(args):
         except SccError as e:
             print(f"[learned: held-out geometry {i} skipped (plain start): {e}]", file=sys.stderr, flush=True)
             pctx.close()
+            torch.cuda.empty_cache()
             continue
         pctx.close()
+        torch.cuda.empty_cache()
         c0 = time.perf_counter()
         yp = net.forward(x[None, :]).to(torch.float64) * ysd_d + ymu_d
         guess = {"t": pca_expand(mt, Ut, yp[:, :kt])[0],
@@ -229,6 +239,7 @@ def learned_main(args):
             failed += 1
             print(f"[learned: held-out geometry {i} failed from the learned start: {e}]", file=sys.stderr, flush=True)
             lctx.close()
+            torch.cuda.empty_cache()
             lctx = mk(1e-10)
             continue
         rl["t_exc"] += t_pred

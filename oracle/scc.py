@@ -453,6 +453,28 @@ def eom_states(h, g, o, t1, t2, nstates, zeta=None, rstates=None, prev=None, met
     return Rs, Ls, np.array(Es), M
 
 
+def canonical_phase(P, R, Lv, zeta, pairs):
+    """Phase of the converged states fixed by the solution alone: the
+    largest-magnitude R1 element of every right vector positive (reading of
+    the phase, which the paper leaves open).  A flipped R_k flips L_k and,
+    for every pair (k, l), O_kl and X3^{kl}; zeta_kl flips with them, so that
+    zeta_kl X3^{kl} (and with it the ground-state amplitudes) is unchanged."""
+    sign = []
+    R, Lv = list(R), list(Lv)
+    for k in range(len(R)):
+        rv = packed_from_state(P, R[k]).numpy()
+        r1 = rv[1:1 + P.nov]
+        s_ = -1.0 if r1[np.argmax(np.abs(r1))] < 0 else 1.0
+        sign.append(s_)
+        if s_ < 0:
+            R[k] = state_from_packed(P, tt(-rv))
+            Lv[k] = state_from_packed(P, -packed_from_state(P, Lv[k]))
+    zeta = zeta.clone()
+    for p, (k, l) in enumerate(pairs):
+        zeta[p] = zeta[p] * sign[k] * sign[l]
+    return R, Lv, zeta
+
+
 def scc_solve(h, g, o, eps, nstates, scc=True, tol=1e-12, maxiter=60,
               start=None, eom_method=None):
     """Ground + excited states with the orthogonality constraints O_kl = 0
@@ -514,6 +536,7 @@ def scc_solve(h, g, o, eps, nstates, scc=True, tol=1e-12, maxiter=60,
             zeta = zeta + step
         else:
             raise RuntimeError("SCC iterations did not converge")
+    R, Lv, zeta = canonical_phase(Packer(o, h.shape[0] - o), R, Lv, zeta, pairs if use_scc else [])
     return Solution(o=o, v=h.shape[0] - o, h=h, L=None, g=g, eps=eps, t1=t1, t2=t2,
                     E0=E0, zeta=zeta, R=R, Lv=Lv, E=np.array(E), scc=use_scc,
                     iters=dict(scc=it))

@@ -156,6 +156,8 @@ class Context:
         if getattr(self, "h", None):
             self.lib.scc_destroy(self.h)
             self.h = None
+        # the workspace goes back to torch's allocator with the context
+        self.workspace = None
 
     def __del__(self):
         try:

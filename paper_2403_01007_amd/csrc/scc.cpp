@@ -823,10 +823,56 @@ std::vector<double> pair_overlaps(scc_ctx* c) {
   return O;
 }
 
-// One solve of the excited states.  warm: continue from the zeta, amplitudes,
-// vectors and zeta Jacobian of a previous pass (the FP64 refinement of a
-// reduced-precision solve); otherwise start from CCSD at zeta = 0.
+// Canonical phase of converged states: the largest-magnitude R1 element of
+// every right vector is positive, whatever the start (plain or a guess) and
+// the path of the iteration.  Flipping R_k flips L_k, the overlaps O_kl and
+// X3^{kl} of every pair with k; zeta_kl changes sign with them (zeta_kl X3^{kl}
+// and so the amplitudes stay as they are), as do the matching rows and
+// columns of the zeta Jacobian.
+void canonical_phase(scc_ctx* c) {
+  const int ns = c->m.d.ns, np = c->m.d.npairs();
+  const int64_t nov = c->sz.nov, nst = c->sz.nst;
+  std::vector<int> sg(ns, 1);
+  std::vector<double> r1(nov);
+  bool any = false;
+  c->sync();
+  for (int k = 0; k < ns; ++k) {
+    c->xfer(r1.data(), c->R[k] + 1, nov * sizeof(double), hipMemcpyDeviceToHost);
+    int64_t im = 0;
+    for (int64_t i = 1; i < nov; ++i)
+      if (std::fabs(r1[i]) > std::fabs(r1[im])) im = i;
+    if (r1[im] < 0) {
+      sg[k] = -1;
+      any = true;
+      c->axpby(0.0, c->R[k], -1.0, c->R[k], nst);
+      c->axpby(0.0, c->Lv[k], -1.0, c->Lv[k], nst);
+    }
+  }
+  if (!any || np == 0) return;
+  std::vector<int> sp;
+  for (int k = 0; k < ns; ++k)
+    for (int l = k + 1; l < ns; ++l) sp.push_back(sg[k] * sg[l]);
+  if ((int)c->zeta.size() == np)
+    for (int p = 0; p < np; ++p) c->zeta[p] *= sp[p];
+  if ((int)c->Jz.size() == np * np)
+    for (int p = 0; p < np; ++p)
+      for (int q = 0; q < np; ++q) c->Jz[p * np + q] *= sp[p] * sp[q];
+  if (c->scc_on) set_scc_inputs(c, c->zeta, true);
+}
+
+int excited_pass_run(scc_ctx* c, double tol, double tol_overlap, bool warm, int& iters);
+
+// One solve of the excited states, returned in the canonical phase.  warm:
+// continue from the zeta, amplitudes, vectors and zeta Jacobian of a previous
+// pass (the FP64 refinement of a reduced-precision solve, or a guess);
+// otherwise start from CCSD at zeta = 0.
 int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& iters) {
+  const int rc = excited_pass_run(c, tol, tol_overlap, warm, iters);
+  if (rc == SCC_OK) canonical_phase(c);
+  return rc;
+}
+
+int excited_pass_run(scc_ctx* c, double tol, double tol_overlap, bool warm, int& iters) {
   const int ns = c->m.d.ns, np = c->m.d.npairs();
   const int maxit = c->opt.max_iter;
   const bool use_scc = c->opt.scc && c->m.d.o >= 2 && np > 0;

@@ -62,6 +62,11 @@ CONFIGS = {
     # the oracle solves completely
     "o6v26": dict(o=6, v=26, nj=70, nstates=3, ncoord=6,
                   nacs=[(0, 1), (0, 2), (1, 2)], sf=0.01, sl=0.01),
+    # three states with all three pairwise couplings at the o4v12 size: the
+    # oracle's complete run (energies, three gradients, three couplings)
+    # takes minutes
+    "o4v12s3": dict(o=4, v=12, nj=48, nstates=3, ncoord=6,
+                    nacs=[(0, 1), (0, 2), (1, 2)], sf=0.01, sl=0.01),
     # tiny systems for determinant-space checks
     "o1v5": dict(o=1, v=5, nj=12, nstates=2, ncoord=2, nacs=[(0, 1)],
                  sf=0.01, sl=0.01),
@@ -72,7 +77,7 @@ CONFIGS = {
 }
 
 CONFIG_SEEDS = {"o4v12": 1001, "o10v90": 1002, "o20v180": 1003,
-                "o4v12x36": 1004, "o30v270": 1005}
+                "o4v12x36": 1004, "o30v270": 1005, "o4v12s3": 1006}
 
 
 @dataclass

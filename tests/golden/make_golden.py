@@ -2,7 +2,7 @@
 
 Calls only oracle/ and synth_inputs/ (seeded synthetic inputs).  Usage:
     python tests/golden/make_golden.py o4v12            (every coupling in both orders)
-    python tests/golden/make_golden.py o6v26 --one-order
+    python tests/golden/make_golden.py o4v12s3 --one-order
 writes tests/golden/<name>.json with energies, zeta, gradients of every
 state and the requested couplings at x = 0.  It also records the oracle's
 own wall time for the whole geometry and for its CCSD ground-state solve

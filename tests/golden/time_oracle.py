@@ -4,7 +4,7 @@ to the whole-geometry time in tests/golden/<name>.json ("oracle_timing").
 
 Calls only oracle/ and synth_inputs/.  Run it with the thread count of the
 golden run (make_golden.py records it), e.g.
-    taskset -c 0-5 python tests/golden/time_oracle.py o6v26
+    taskset -c 4-7 python tests/golden/time_oracle.py o4v12s3
 """
 import json
 import os

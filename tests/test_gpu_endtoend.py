@@ -382,26 +382,29 @@ def test_failure_paths():
     assert e.value.code == -1
 
 
-def test_o6v26_batched_targets_against_stored_oracle():
+@pytest.mark.parametrize("name", ["o4v12s3", "o6v26"])
+def test_three_state_batched_targets_against_stored_oracle(name):
     """Three states, their three gradients and the three couplings (0,1),
     (0,2), (1,2) over six coordinates, all targets solved in lockstep by
     scc_gradients_and_couplings (the path the benchmark times), against
     values written by tests/golden/make_golden.py, which calls only the
-    oracle (its Davidson EOM path at this size)."""
-    path = os.path.join(HERE, "golden", "o6v26.json")
+    oracle (dense EOM at o4v12s3, Davidson at o6v26)."""
+    path = os.path.join(HERE, "golden", f"{name}.json")
     if not os.path.exists(path):
-        pytest.skip("tests/golden/o6v26.json not written yet")
+        pytest.skip(f"tests/golden/{name}.json not written (the oracle's complete o6v26 run takes hours)")
     with open(path) as f:
         ref = json.load(f)
     from paper_2403_01007_amd import Context
-    S = make_system("o6v26")
+    S = make_system(name)
     assert (S.seed, S.reading, S.o, S.v, S.nj) == (ref["seed"], ref["reading"], ref["o"], ref["v"], ref["nj"])
-    print("[o6v26 golden, batched targets]", flush=True)
+    print(f"[{name} golden, batched targets]", flush=True)
     h, L = S.at(np.zeros(S.ncoord))
     ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
     ctx.set_hamiltonian(h, L)
     E, z, _ = ctx.excited()
     e0 = float(ctx.get(3).cpu()[0])
+    print(f"  E0 err {abs(e0 - ref['E0']):.2e}, E err {np.abs(E - np.asarray(ref['E'])).max():.2e}, "
+          f"zeta err {np.abs(z - np.asarray(ref['zeta'])).max():.2e}", flush=True)
     assert abs(e0 - ref["E0"]) < E_TOL
     assert np.abs(E - np.asarray(ref["E"])).max() < E_TOL
     assert np.abs(z - np.asarray(ref["zeta"])).max() < 1e-7
