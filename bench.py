@@ -78,12 +78,18 @@ def oracle_baseline(S, workload, iterations=25):
     ht = torch.as_tensor(h)
     gt = cc.chol_to_g(torch.as_tensor(L))
     eps = np.diag(cc.fock(ht, gt, S.o).numpy()).copy()
-    c0 = time.perf_counter()
-    try:
-        oscc.solve_ground(ht, gt, S.o, eps, tol=0.0, maxiter=iterations)
-    except RuntimeError:
-        pass  # tol = 0: the iteration always stops at its step limit
-    t_step = (time.perf_counter() - c0) / iterations
+
+    def steps(n):
+        c0 = time.perf_counter()
+        try:
+            oscc.solve_ground(ht, gt, S.o, eps, tol=0.0, maxiter=n)
+        except RuntimeError:
+            pass  # tol = 0: the iteration always stops at its step limit
+        return time.perf_counter() - c0
+
+    # a two-step probe sizes the sample to about 20 s of CPU work
+    iterations = int(min(iterations, max(2, round(20.0 / max(steps(2) / 2, 1e-3)))))
+    t_step = steps(iterations) / iterations
     ratio = (ref["solve_seconds"] + ref["targets_seconds"]) / ref["ground_iteration_seconds"]
     return {"value": t_step * ratio, "unit": "s/geometry", "cores": threads, "kind": "oracle",
             "sample": (f"{iterations} steps of the oracle's CCSD ground-state iteration at {workload} "
@@ -118,7 +124,8 @@ def learned_main(args):
 
     S = make_system(args.learned_workload)
     dev = torch.device("cuda:0")
-    mk = lambda tol: Context(S.o, S.v, S.nj, S.nstates, tol=tol, tol_overlap=0.1 * tol)
+    mk = lambda tol, verbose=False: Context(S.o, S.v, S.nj, S.nstates, tol=tol, tol_overlap=0.1 * tol,
+                                            verbose=verbose)
     ns, npair = S.nstates, S.nstates * (S.nstates - 1) // 2
     states, pairs = list(range(ns)), list(S.nacs)
     nt = len(states) + len(pairs)
@@ -130,12 +137,12 @@ def learned_main(args):
         ctx.set_hamiltonian_fixed_basis(torch.as_tensor(h, device=dev), torch.as_tensor(L, device=dev))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        it_g, fb = 0, 0
+        it_g, fb_g = 0, 0
         if guess is not None:
             _, info = ctx.ground(guess["t"])
-            it_g, fb = info.iterations, info.fallback_used
+            it_g, fb_g = info.iterations, info.fallback_used
         E, z, info = ctx.excited(None if guess is None else guess["r"])
-        it_e, fb = info.iterations + it_g, fb or info.fallback_used
+        it_e, fb_e = info.iterations + it_g, info.fallback_used
         torch.cuda.synchronize()
         t_exc = time.perf_counter() - t0
         res = ctx.gradients_and_couplings(states, pairs, dh, dL, guess=None if guess is None else guess["m"],
@@ -143,7 +150,8 @@ def learned_main(args):
         g, d, info = res[:3]
         torch.cuda.synchronize()
         out = dict(E=np.asarray(E), zeta=np.asarray(z), g=g, d=d, t_exc=t_exc, t_all=time.perf_counter() - t0,
-                   it_exc=it_e, it_mult=info.iterations, fallback=fb or info.fallback_used)
+                   it_exc=it_e, it_mult=info.iterations, fallback=fb_g or fb_e or info.fallback_used,
+                   fb=(fb_g, fb_e, info.fallback_used))
         if keep:
             out["M"] = res[3]
         return out
@@ -213,7 +221,7 @@ def learned_main(args):
     # held-out geometries at the benchmark tolerance: plain start on a fresh
     # context each, learned start on one context along the held-out sequence
     plain, learned = [], []
-    lctx = mk(1e-10)
+    lctx = mk(1e-10, args.verbose)
     failed = 0
     for i, x in enumerate(Xte):
         pctx = mk(1e-10)
@@ -240,14 +248,15 @@ def learned_main(args):
             print(f"[learned: held-out geometry {i} failed from the learned start: {e}]", file=sys.stderr, flush=True)
             lctx.close()
             torch.cuda.empty_cache()
-            lctx = mk(1e-10)
+            lctx = mk(1e-10, args.verbose)
             continue
         rl["t_exc"] += t_pred
         rl["t_all"] += t_pred
         plain.append(rp)
         learned.append(rl)
         print(f"[learned: held-out {i}: plain {rp['t_all']:.1f} s ({rp['it_exc']}+{rp['it_mult']} it), learned "
-              f"{rl['t_all']:.1f} s ({rl['it_exc']}+{rl['it_mult']} it)]", file=sys.stderr, flush=True)
+              f"{rl['t_all']:.1f} s ({rl['it_exc']}+{rl['it_mult']} it), fallbacks ground/excited/multipliers "
+              f"{rl['fb']}]", file=sys.stderr, flush=True)
     mean = lambda rs, key: float(np.mean([r[key] for r in rs]))
     diff = lambda key: max(float(np.abs(np.asarray(a[key]) - np.asarray(b[key])).max()) for a, b in zip(plain, learned))
     line = {
@@ -266,6 +275,7 @@ def learned_main(args):
                     "plain_iterations_multipliers": mean(plain, "it_mult"),
                     "learned_iterations_multipliers": mean(learned, "it_mult"),
                     "fallbacks": int(sum(r["fallback"] for r in learned)),
+                    "fallbacks_ground_excited_multipliers": [int(sum(r["fb"][q] for r in learned)) for q in range(3)],
                     "max_abs_diff_energy": diff("E"), "max_abs_diff_gradient": diff("g"),
                     "max_abs_diff_coupling": diff("d"),
                     "training_data_s": t_data, "training_s": t_train, "final_loss": float(losses[-20:].mean())},

@@ -157,11 +157,14 @@ int scc_ground(scc_ctx* ctx, const double* guess_t, double* e0, scc_info* info);
  * SCC orthogonality conditions O_kl = <psi_k|P|psi_l> = 0 imposed through
  * zeta_kl X3^kl, ground and excited states solved simultaneously (SCC
  * section; natural projection).  Normalisation: O_kk = 1 and calL_k.calR_k =
- * 1; phase: largest |R1| element positive; order: ascending energy.
+ * 1; phase: the largest-magnitude R1 element of each converged right vector
+ * is positive, whatever the start (zeta_kl changes sign with a flipped state,
+ * so zeta_kl X3^kl does not); order: ascending energy.
  * energies: device double[nstates] (total energies);
  * zeta: device double[nstates*(nstates-1)/2] (pairs k<l, row-major).
- * guess: NULL (plain start: CCSD states at zeta = 0 from unit vectors on
- * the lowest singles) or [nstates][1 + nov + nov^2] right vectors followed
+ * guess: NULL (plain start: CCSD states at zeta = 0, Davidson started from
+ * the lowest eigenvectors of the singles block of calHbar at t = 0) or
+ * [nstates][1 + nov + nov^2] right vectors followed
  * by [npairs] zeta values; the solve then starts there (amplitudes from the
  * preceding scc_ground or scc_excited; the SCC Jacobian dO/dzeta of the
  * context's previous solve, if any, seeds the zeta updates) and falls back

@@ -293,6 +293,13 @@ int ground_solve(scc_ctx* c, double tol, int maxit, double& rn) {
     c->log("  ground it %3d  |Omega| %.3e\n", it, rn);
     c->last_ground_its = it;
     if (rn < tol) break;
+    // a residual that is not finite, or four orders of magnitude above the
+    // best one reached, will not come back: stop at once
+    if (!std::isfinite(rn) || (it > 0 && rn > 1e4 * best)) {
+      c->last_ground_its = it;
+      c->err = "ground-state iterations diverged";
+      return SCC_ENOCONV;
+    }
     // restart the extrapolation when it stagnates
     if (rn < best) {
       best = rn;
