@@ -150,7 +150,9 @@ int scc_set_hamiltonian_fixed_basis(scc_ctx* ctx, const double* h, const double*
  * eq. for Omega_mu).  guess_t: NULL or [t1 | t2]; a guess is used only if
  * its residual norm is below that of the plain start (the MP2 amplitudes),
  * else info->fallback_used = 1.  e0: device double[1].  The converged
- * amplitudes are the starting point of a following scc_excited. */
+ * amplitudes are the starting point of a following scc_excited.
+ * SCC_ENOCONV at the iteration limit, or at once when the residual norm is
+ * not finite or has grown 10^4 times above the best one reached. */
 int scc_ground(scc_ctx* ctx, const double* guess_t, double* e0, scc_info* info);
 
 /* Excited states of the constrained set: EOM right/left eigenvectors with the

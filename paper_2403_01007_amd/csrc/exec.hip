@@ -1404,7 +1404,7 @@ ContractPlan plan_contract(const Graph& g, const Op& op, double* arena, double* 
   const int64_t lim32 = (int64_t)1 << 31;
   const bool two_ok = !(Bx == 1 && (Mx == 1 || Nx == 1)) && dA.size() < lim32 && dB.size() < lim32 &&
                       dO.size() < lim32;
-  constexpr double GEMM_RATE = 30e12, TWO_PENALTY = 1.07, TWO_PENALTY_SHORT = 1.3, HBM_RATE = 3e12, LAUNCH_S = 4e-6;
+  constexpr double GEMM_RATE = 40e12, TWO_PENALTY = 1.35, TWO_PENALTY_SHORT = 1.6, HBM_RATE = 3e12, LAUNCH_S = 4e-6;
   const double gemm_s = 2.0 * Mx * Nx * Kx * Bx / GEMM_RATE;
   auto move_s = [&](int64_t elems) { return 16.0 * elems / HBM_RATE + LAUNCH_S; };
   bool two = false;

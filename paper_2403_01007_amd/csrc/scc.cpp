@@ -553,6 +553,8 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
   std::vector<double> G(maxsub * maxsub, 0.0);
   int nw = 0, ng = 0;
   iters = 0;
+  double stag_ref = 1e300;
+  int stag_it = 0;
   for (int it = 0; it < maxit; ++it) {
     iters = it + 1;
     if (nw < nv) {
@@ -672,6 +674,14 @@ int davidson(scc_ctx* c, bool left, int nroots, const std::vector<const double*>
         std::snprintf(msg, sizeof msg, "excited state %d converged to a complex energy %.10f %+.3ei", k, a, b);
         throw SccError(SCC_ECOMPLEX, msg);
       }
+    }
+    // stagnation (e.g. a complex pair that neither converges nor separates):
+    // no halving of the largest wanted residual in 60 steps ends the solve
+    if (maxres < 0.5 * stag_ref) {
+      stag_ref = maxres;
+      stag_it = it;
+    } else if (it - stag_it >= 60) {
+      throw SccError(SCC_ENOCONV, "Davidson iterations stagnated");
     }
     if (c->opt.verbose) {
       c->log("  %s davidson it %3d  nv %2d  max|r| %.3e", left ? "left " : "right", it, nv, maxres);
