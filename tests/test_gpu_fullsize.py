@@ -88,3 +88,37 @@ def test_fullsize_left_adjoint(full):
     val = float(left @ _flat(r))
     print(f"  <l, sigma(r)> {ref:.15e}  <sigma_L(l), r> {val:.15e}", flush=True)
     assert abs(val - ref) < 1e-11 * max(1.0, abs(ref))
+
+
+def test_fullsize_gradients_match_finite_differences():
+    """o10v90 in the fixed basis at a geometry of the trajectory family: the
+    analytic gradients of the three states along one coordinate, from the
+    lockstep path the benchmark times (multipliers of all targets,
+    orbital response, densities, derivative contraction), against the
+    5-point central difference of each state's energy, every displaced
+    geometry solved from scratch (RHF, ground and excited states).  With
+    h = 2e-3 the truncation error is below 1e-11; energies converged to
+    about 1e-12 give a difference error of about 18e-12 / (12 h) ~ 1e-9."""
+    from paper_2403_01007_amd import Context
+    from synth_inputs import family_geometries
+    S = make_system("o10v90")
+    print("[case o10v90 gradients against finite differences]", flush=True)
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
+    x0 = family_geometries(S.ncoord, [20000])[0]
+    k, h = 3, 2e-3
+    ctx.set_hamiltonian_fixed_basis(*S.at(x0))
+    ctx.excited()
+    states = list(range(S.nstates))
+    g, _, _ = ctx.gradients_and_couplings(states, list(S.nacs), S.dh, S.dL)
+    E = {}
+    for s in (-2, -1, 1, 2):
+        x = x0.copy()
+        x[k] += s * h
+        ctx.set_hamiltonian_fixed_basis(*S.at(x))
+        E[s], _, _ = ctx.excited()
+        print(f"  displacement {s:+d}: energies {E[s]}", flush=True)
+    for n in states:
+        fd = (E[-2][n] - 8 * E[-1][n] + 8 * E[1][n] - E[2][n]) / (12 * h)
+        print(f"  state {n}: analytic {g[n][k]:.12e}  finite difference {fd:.12e}  diff {abs(g[n][k] - fd):.2e}",
+              flush=True)
+        assert abs(g[n][k] - fd) < 1e-8
