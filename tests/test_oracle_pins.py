@@ -281,3 +281,34 @@ def test_davidson_states_match_dense_eigenvectors(name):
         for i in range(3):
             assert float(torch.abs(torch.as_tensor(a.R[k][i]) - torch.as_tensor(b.R[k][i])).max()) < 1e-10
             assert float(torch.abs(torch.as_tensor(a.Lv[k][i]) - torch.as_tensor(b.Lv[k][i])).max()) < 1e-10
+
+
+def test_canonical_phase_is_a_symmetry(o2v4_solution):
+    """Reading of the phase: each converged right vector has its
+    largest-magnitude R1 element positive.  Flipping a state together with
+    zeta of its pairs is an exact symmetry of the SCC equations (X3^{kl} is
+    bilinear in R_k and R_l, so zeta_kl X3^{kl} is unchanged): the residual
+    is the same to rounding, and the canonical phase maps the flipped
+    solution back onto the converged one."""
+    S, sol, _ = o2v4_solution
+    P = scc.Packer(S.o, S.v)
+    for k in range(S.nstates):
+        r1 = scc.packed_from_state(P, sol.R[k]).numpy()[1:1 + P.nov]
+        assert r1[np.argmax(np.abs(r1))] > 0
+    flip = lambda st: scc.state_from_packed(P, -scc.packed_from_state(P, st))
+    R2 = [flip(sol.R[0]), sol.R[1]]
+    L2 = [flip(sol.Lv[0]), sol.Lv[1]]
+    z2 = -sol.zeta
+    a = cc.residual(sol.h, sol.g, sol.t1, sol.t2, S.o, sol.zeta, sol.R)
+    b = cc.residual(sol.h, sol.g, sol.t1, sol.t2, S.o, z2, R2)
+    for x, y in zip(a, b):
+        assert float(torch.abs(torch.as_tensor(x) - torch.as_tensor(y)).max()) < 1e-14
+    # flipping only the state (zeta kept) changes the residual at first order
+    c = cc.residual(sol.h, sol.g, sol.t1, sol.t2, S.o, sol.zeta, R2)
+    assert float(torch.abs(torch.as_tensor(c[2]) - torch.as_tensor(a[2])).max()) > 1e-6
+    R3, L3, z3 = scc.canonical_phase(P, R2, L2, z2, cc.pair_list(S.nstates))
+    assert float(torch.abs(z3 - sol.zeta).max()) == 0.0
+    for k in range(S.nstates):
+        for i in range(3):
+            assert float(torch.abs(torch.as_tensor(R3[k][i]) - torch.as_tensor(sol.R[k][i])).max()) == 0.0
+            assert float(torch.abs(torch.as_tensor(L3[k][i]) - torch.as_tensor(sol.Lv[k][i])).max()) == 0.0
