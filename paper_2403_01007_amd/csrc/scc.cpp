@@ -60,11 +60,11 @@ Sizes sizes_for(const Dims& d) {
   s.nvt = s.nov + s.nov * s.nov;
   s.nst = 1 + s.nvt;
   s.nlag = s.nvt + d.ns * (s.nst + 1) + d.npairs();
-  // Davidson search space: 16 vectors per working root, at most 24 GB for
+  // Davidson search space: 32 vectors per working root, at most 24 GB for
   // the vectors and their images; a thick restart keeps three Ritz vectors
   // per working root
   const int nwork = d.ns + 2;
-  s.maxsub = std::max(40, std::min<int>(16 * nwork, (int)(24e9 / (16.0 * up(s.nvt)))));
+  s.maxsub = std::max(40, std::min<int>(32 * nwork, (int)(24e9 / (16.0 * up(s.nvt)))));
   s.nkeep = std::min(s.maxsub / 2, 3 * nwork);
   int64_t p = 0;
   p += up(s.nvt) + up(s.nov);           // D, Dk
@@ -889,6 +889,10 @@ int excited_pass(scc_ctx* c, double tol, double tol_overlap, bool warm, int& ite
   return rc;
 }
 
+// residual tolerance of the solves behind the finite-difference zeta
+// Jacobian (step 1e-4: O to about 1e-8 gives the Jacobian to about 1e-4)
+constexpr double FD_TOL = 1e-8;
+
 int excited_pass_run(scc_ctx* c, double tol, double tol_overlap, bool warm, int& iters) {
   const int ns = c->m.d.ns, np = c->m.d.npairs();
   const int maxit = c->opt.max_iter;
@@ -900,8 +904,9 @@ int excited_pass_run(scc_ctx* c, double tol, double tol_overlap, bool warm, int&
     c->Jz.clear();
     set_scc_inputs(c, c->zeta, false);
     // with the constraint active, the CCSD states are only the starting
-    // point: left vectors are solved once, at the converged SCC point
-    rc = excited_at_fixed_zeta(c, tol, maxit, false, iters, !use_scc);
+    // point (solved to 1e-8, the accuracy of the finite-difference Jacobian
+    // that follows): left vectors are solved once, at the converged SCC point
+    rc = excited_at_fixed_zeta(c, use_scc ? std::max(tol, FD_TOL) : tol, maxit, false, iters, !use_scc);
     if (rc) return rc;
   } else if (!use_scc) {
     for (int k = 0; k < ns; ++k) c->cp(c->Lv[k], c->R[k], c->sz.nst);
@@ -942,9 +947,10 @@ int excited_pass_run(scc_ctx* c, double tol, double tol_overlap, bool warm, int&
     for (int it = 0; it < c->opt.max_iter && !conv; ++it) {
       // inexact inner solves while the constraint is far from satisfied;
       // the pass that is the base point of a finite-difference Jacobian is
-      // tight (a Jacobian carried over from a previous solve needs none)
+      // as tight as its displaced solves (a Jacobian carried over from a
+      // previous solve needs none)
       const bool fd_base = it == 0 && Jz.empty();
-      const double tol_it = fd_base ? tol : std::max(tol, std::min(1e-5, 1e-3 * omax_prev));
+      const double tol_it = fd_base ? std::max(tol, FD_TOL) : std::max(tol, std::min(1e-5, 1e-3 * omax_prev));
       for (size_t p = 0; p < c->m.zeta.size(); ++p) c->set_scalar(c->m.zeta[p], z[p]);
       for (int k = 0; k < ns; ++k) c->put_state(c->m.xs[k], Rx[k]);
       rc = excited_at_fixed_zeta(c, tol_it, maxit, true, iters, false);
@@ -988,7 +994,7 @@ int excited_pass_run(scc_ctx* c, double tol, double tol_overlap, bool warm, int&
           c->cp(keepL[k], c->Lv[k], nst);
         }
         // the displaced solves need O to ~1e-8 only (h = 1e-4)
-        const double tol_fd = std::max(tol_it, 1e-8);
+        const double tol_fd = std::max(tol_it, FD_TOL);
         for (int p = 0; p < np; ++p) {
           std::vector<double> zp = z;
           zp[p] += h;
