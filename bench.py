@@ -320,7 +320,7 @@ def main():
                     help="only the 512 MiB device copy that scales HBM traffic counters, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (there is no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.learned:
