@@ -71,6 +71,30 @@ def test_o2v4_against_live_oracle(scc):
     _compare(S, gpu, sol.E0, sol.E, zeta, grads, nacs)
 
 
+def test_single_state_has_no_constraint():
+    """One excited state: no pair, so no zeta and no orthogonality condition;
+    the SCCSD state is the EOM-CCSD state.  Energy and gradient of the state
+    through the lockstep path (one target, no couplings) against the live
+    oracle."""
+    from oracle import scc as oscc
+    from paper_2403_01007_amd import Context
+    S = make_system("o2v4", nstates=1, nacs=[])
+    print("[o2v4 one state]", flush=True)
+    h, L = S.at(np.zeros(S.ncoord))
+    ctx = Context(S.o, S.v, S.nj, S.nstates, tol=1e-11, tol_overlap=1e-12)
+    ctx.set_hamiltonian(h, L)
+    E, _, _ = ctx.excited()
+    e0 = float(ctx.get(3).cpu()[0])
+    g, d, _ = ctx.gradients_and_couplings([0], [], S.dh, S.dL)
+    sol = oscc.solve_system(S)
+    ref = oscc.gradient_and_nacs(S, sol, [("grad", 0)])[("grad", 0)]["value"]
+    assert abs(e0 - sol.E0) < E_TOL
+    assert abs(E[0] - sol.E[0]) < E_TOL
+    err = np.abs(g[0] - np.asarray(ref)).max()
+    print(f"  grad max err {err:.2e}", flush=True)
+    assert err < G_TOL
+
+
 def test_o4v12_against_stored_oracle():
     """o4v12 (two states, SCC active) against values written by
     tests/golden/make_golden.py, which calls only the oracle."""
