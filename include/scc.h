@@ -178,8 +178,14 @@ int scc_excited(scc_ctx* ctx, int nstates, const double* guess, double* energies
  * of the coupling d_mn (kind = 1): the stationarity conditions of the
  * gradient / coupling Lagrangians (eqs. Lagrangian_gradient,
  * Lagrangian_coupling) solved for the amplitude, excited-state and
- * orthogonality multipliers first, then the orbital multipliers. */
-int scc_multipliers(scc_ctx* ctx, int kind, int m, int n, scc_info* info);
+ * orthogonality multipliers first, then the orbital multipliers.
+ * guess: NULL or device double[scc_multiplier_length] starting multipliers,
+ * used only if the residual b - J^T x0 is below that of the zero start (else
+ * info->fallback_used = 1).  multipliers: NULL or device
+ * double[scc_multiplier_length], receives the converged multipliers (layout
+ * at scc_multiplier_length). */
+int scc_multipliers(scc_ctx* ctx, int kind, int m, int n, const double* guess, double* multipliers,
+                    scc_info* info);
 
 /* Effective densities of one target: the gradient of state n (kind = 0, m
  * ignored) or the coupling d_mn (kind = 1).  They are the one- and

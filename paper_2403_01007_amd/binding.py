@@ -77,7 +77,7 @@ def load_library():
     lib.scc_set_hamiltonian_fixed_basis.argtypes = [P, P, P, D, P, P, ctypes.POINTER(Info)]
     lib.scc_ground.argtypes = [P, P, P, ctypes.POINTER(Info)]
     lib.scc_excited.argtypes = [P, I, P, P, P, ctypes.POINTER(Info)]
-    lib.scc_multipliers.argtypes = [P, I, I, I, ctypes.POINTER(Info)]
+    lib.scc_multipliers.argtypes = [P, I, I, I, P, P, ctypes.POINTER(Info)]
     lib.scc_densities.argtypes = [P, I, I, I, P, P, P]
     lib.scc_gradient.argtypes = [P, I, I, P, P, P, ctypes.POINTER(Info)]
     lib.scc_nac.argtypes = [P, I, I, I, P, P, P, ctypes.POINTER(Info)]
@@ -215,10 +215,15 @@ class Context:
                     "scc_excited")
         return e.cpu().numpy(), z.cpu().numpy()[:self.ns * (self.ns - 1) // 2], info
 
-    def multipliers(self, kind, m, n):
+    def multipliers(self, kind, m, n, guess=None, out=False):
+        """Multipliers of one target; returns info, plus the converged multipliers (device
+        [multiplier_length]) when out=True.  guess: starting multipliers of that length."""
         info = Info()
-        self._check(self.lib.scc_multipliers(self.h, kind, m, n, ctypes.byref(info)), "scc_multipliers")
-        return info
+        g = None if guess is None else self._dev(guess)
+        x = self.zeros(self.multiplier_length()) if out else None
+        self._check(self.lib.scc_multipliers(self.h, kind, m, n, _ptr(g), _ptr(x), ctypes.byref(info)),
+                    "scc_multipliers")
+        return (info, x) if out else info
 
     def densities(self, kind, m, n):
         """Effective densities of the gradient of state n (kind 0) or of the

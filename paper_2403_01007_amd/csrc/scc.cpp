@@ -2456,7 +2456,7 @@ int scc_excited(scc_ctx* c, int nstates, const double* guess, double* energies, 
   });
 }
 
-int scc_multipliers(scc_ctx* c, int kind, int m, int n, scc_info* info) {
+int scc_multipliers(scc_ctx* c, int kind, int m, int n, const double* guess, double* multipliers, scc_info* info) {
   if (!c) return SCC_EINVAL;
   const int ns = c->m.d.ns;
   if (kind < 0 || kind > 1 || n < 0 || n >= ns || (kind == 1 && (m < 0 || m >= ns || m == n))) {
@@ -2467,7 +2467,12 @@ int scc_multipliers(scc_ctx* c, int kind, int m, int n, scc_info* info) {
     c->err = "scc_multipliers before scc_excited";
     return SCC_ESTATE;
   }
-  return guarded(c, info, [&]() -> int { return multipliers_solve(c, kind, m, n, info); });
+  return guarded(c, info, [&]() -> int {
+    bool rejected = false;
+    const int rc = multipliers_solve(c, kind, m, n, info, guess, multipliers, &rejected);
+    if (info && rejected) info->fallback_used = 1;
+    return rc;
+  });
 }
 
 int scc_densities(scc_ctx* c, int kind, int mm, int nn, double* d1, double* z3, double* kappa_bar) {

@@ -472,3 +472,18 @@ def test_multiplier_guesses():
     g3, d3, info3 = ctx.gradients_and_couplings(states, pairs, S.dh, S.dL, guess=bad)
     assert info3.fallback_used == 1
     assert np.abs(g3 - g0).max() < G_TOL and np.abs(d3 - d0).max() < G_TOL
+    # one target through scc_multipliers (the gradient of state 0, the first
+    # lockstep target): the same multipliers, restarted from the lockstep
+    # ones in fewer steps, and a guess that is not finite dropped
+    ctx.excited()  # the same states again; the single-target Krylov space starts empty
+    i_zero, x0 = ctx.multipliers(0, 0, 0, out=True)
+    rel = float(torch.abs(x0 - M[0]).max() / torch.abs(M[0]).max())
+    print(f"  single target: {i_zero.iterations} iterations from zero, max relative difference from the "
+          f"lockstep multipliers {rel:.1e}", flush=True)
+    assert rel < 1e-6
+    i_warm = ctx.multipliers(0, 0, 0, guess=M[0])
+    print(f"  single target from the lockstep multipliers: {i_warm.iterations} iterations", flush=True)
+    assert i_warm.fallback_used == 0 and i_warm.iterations < i_zero.iterations
+    i_bad, x_bad = ctx.multipliers(0, 0, 0, guess=torch.full_like(M[0], float("nan")), out=True)
+    assert i_bad.fallback_used == 1
+    assert float(torch.abs(x_bad - x0).max() / torch.abs(x0).max()) < 1e-6
