@@ -274,6 +274,13 @@ __device__ __forceinline__ void gemm_multi_body(const GemmMulti& G,
     const double* B = S.B + bz * S.sBb;
     const bool a_kfast = (S.sAk == 1);
     const bool b_nfast = (S.sBn == 1) || (S.sBk != 1);
+    // the segment's summed-index maps in scalar registers for the whole K
+    // loop (read through the dynamic segment index, they would otherwise be
+    // fetched again from the argument block before every load)
+    auto sreg = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
+    const IdxMap mAk{sreg(S.mAk.D), sreg(S.mAk.so), sreg(S.mAk.mag), sreg(S.mAk.sh)};
+    const IdxMap mBk{sreg(S.mBk.D), sreg(S.mBk.so), sreg(S.mBk.mag), sreg(S.mBk.sh)};
+    const int64_t sAk = (int64_t)sreg((uint32_t)S.sAk), sBk = (int64_t)sreg((uint32_t)S.sBk);
     auto a_pos = [&](int e, int& mm, int& kk) {
       const int idx = tid + e * GEMM_THREADS;
       if (a_kfast) {
@@ -316,14 +323,14 @@ __device__ __forceinline__ void gemm_multi_body(const GemmMulti& G,
         int mm, kk;
         a_pos(e, mm, kk);
         const int64_t gm = m0 + mm, gk = k0 + kk;
-        ra[e] = (gm < a.M && gk < le) ? A[aoff[e] + imap32((uint32_t)gk, S.mAk, S.sAk)] : 0.0;
+        ra[e] = (gm < a.M && gk < le) ? A[aoff[e] + imap32((uint32_t)gk, mAk, sAk)] : 0.0;
       }
 #pragma unroll
       for (int e = 0; e < EB; ++e) {
         int nn, kk;
         b_pos(e, nn, kk);
         const int64_t gn = n0 + nn, gk = k0 + kk;
-        rb[e] = (gn < a.N && gk < le) ? B[boff[e] + imap32((uint32_t)gk, S.mBk, S.sBk)] : 0.0;
+        rb[e] = (gn < a.N && gk < le) ? B[boff[e] + imap32((uint32_t)gk, mBk, sBk)] : 0.0;
       }
     };
     const double alpha = S.alpha;
