@@ -260,7 +260,7 @@ def davidson(apply, diag, nroots, guesses, tol, maxit=400, maxsub=None, nbuf=2):
     search space; a wanted root that converges complex is an error."""
     n = diag.size
     nwork = nroots + nbuf
-    maxsub = maxsub or max(40, 8 * nwork)
+    maxsub = maxsub or max(40, 32 * nwork)
     V, W = [], []
 
     def add(vec):
